@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of SCOUP's sparse-code uplift on one MI355X.
+
+One step = the whole uplift of Algorithm 1 over one synthetic scene already
+resident in HBM: for every view, projection, tile binning, per-tile depth
+sort, front-to-back compositing fused with the weighted sparse accumulation
+(Eq. 2, Eq. 5), then the Top-K filter of every Gaussian (Eq. 6).
+
+Default workload ("scene"): 1,000,000 anisotropic Gaussians in a 10x10x4 box,
+200 views of 1008x756 on a jittered orbit, 120 Voronoi regions per view,
+8-sparse codes over M=256 atoms, Top-K=8.  The metric is Gaussian-pixel
+contributions aggregated per second (terms e_i(v,p) > 0 that enter Eq. 5).
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build measures a
+single GPU (the multi-GPU plan is in the design notes).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 not used
+STAGES = ["project", "tile_scan", "emit", "dense_tile_sort", "composite_accumulate", "topk",
+          "render", "decode", "render_backward", "backward_gemm"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_contribution(k_code: int) -> int:
+    """Algorithmic flops of one contribution: alpha (2 offsets, 6 for the
+    quadratic form, exp, opacity product, clamp = 11), compositing (1 - alpha,
+    T(1 - alpha), alpha T, cutoff test = 4) and Algorithm 1's inner loop
+    (k_code multiply-adds = 2 k_code)."""
+    return 15 + 2 * k_code
+
+
+def cpu_baseline(sc, rows=192):
+    """The FP64 oracle on a bounded sample: all Gaussians, view 0, a band of
+    ``rows`` image rows through the centre (projection + compositing +
+    accumulation), single process."""
+    import numpy as np
+    from oracle import composite as OC
+    from oracle import project as OP
+    from oracle import uplift as OU
+    cam = sc.views.cameras[0]
+    y0 = max(0, cam.height // 2 - rows // 2)
+    mask = np.zeros(cam.width * cam.height, bool)
+    mask[y0 * cam.width:(y0 + rows) * cam.width] = True
+    acc = np.zeros((sc.gaussians.n, sc.views.m_atoms))
+    t0 = time.perf_counter()
+    proj = OP.project(sc.gaussians, cam)
+    vw = OC.composite_view(proj, cam.width, cam.height, pixel_mask=mask, track_marginal=False)
+    OU.accumulate_view(acc, None, vw, sc.views.region_maps[0], int(sc.views.region_base[0]),
+                       sc.views.code_idx, sc.views.code_val, None, sc.views.m_atoms)
+    dt = time.perf_counter() - t0
+    return dict(value=vw.n_contrib / dt, unit="contributions/s", cores=1, kind="oracle",
+                sample=f"view 0, rows {y0}..{y0 + rows - 1} of {cam.width}x{cam.height}, "
+                       f"all {sc.gaussians.n} Gaussians: {vw.n_contrib} contributions in {dt:.1f} s "
+                       f"(FP64 NumPy, one process)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scene", choices=["scene", "tiny", "large"])
+    ap.add_argument("--views", type=int, default=None, help="use only the first views (debug)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(views shard across GPUs by design, but no multi-GPU path is built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenegen as sg
+    import paper_2605_13600_amd as P
+    from paper_2605_13600_amd import _lib as L
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lib = L.load()
+
+    t = time.time()
+    sc = sg.make_scene(args.workload, n_views=args.views)
+    log(f"scene {args.workload}: {sc.gaussians.n} Gaussians, {sc.views.n_views} views "
+        f"{sc.views.cameras[0].width}x{sc.views.cameras[0].height}, M={sc.views.m_atoms}, "
+        f"K={sc.k_top} generated in {time.time() - t:.1f}s")
+    dg = P.gaussians_to_device(sc.gaussians)
+    dv = P.views_to_device(sc.views)
+    n, m, k = sc.gaussians.n, sc.views.m_atoms, sc.k_top
+    acc = torch.empty((n, m), dtype=torch.float32, device="cuda")
+    ws = P.api.Workspace()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        a, nc = P.uplift_accumulate(dg, dv, acc=acc, workspace=ws)
+        idx, val = P.topk(a, k)
+        return nc
+
+    for i in range(args.warmup):
+        nc = step()
+        log(f"warmup {i} done, contributions {nc}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        nc = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms:.2f} ms/step, {nc} contributions/step")
+
+    # per-stage kernel time with HIP events on the launch stream (one extra step)
+    lib.scoup_stage_timing(1)
+    step()
+    stages = {}
+    for sid, name in enumerate(STAGES):
+        tot, cnt = C.c_double(), C.c_int64()
+        lib.scoup_stage_stats(sid, C.byref(tot), C.byref(cnt))
+        if cnt.value:
+            stages[name] = dict(total_ms=round(tot.value, 4), launches=int(cnt.value),
+                                avg_us=round(tot.value * 1e3 / cnt.value, 3))
+    lib.scoup_stage_timing(0)
+    log(f"stages: {json.dumps(stages)}")
+
+    # roofline of the dominant kernel (compositing + accumulation, one launch per view)
+    dom = max(stages, key=lambda s: stages[s]["total_ms"])
+    comp = stages["composite_accumulate"]
+    per_launch_flops = nc / sc.views.n_views * flops_per_contribution(sc.views.k_code)
+    achieved = per_launch_flops / (comp["avg_us"] * 1e-6) / 1e12
+    roofline = dict(kernel="composite_accumulate", dominant_stage=dom, bound="alu",
+                    achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 5), traffic=None,
+                    per_launch=f"{nc / sc.views.n_views:.4g} contributions x "
+                               f"{flops_per_contribution(sc.views.k_code)} flops")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the CPU sample ...")
+        cpu = cpu_baseline(sc)
+        log(f"cpu baseline: {cpu}")
+
+    w = sc.views.cameras[0]
+    out = {
+        "metric": "Gaussian-pixel contributions aggregated/s (uplift)",
+        "value": nc * args.steps / dt,
+        "unit": "contributions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload} uplift: {n} Gaussians, {sc.views.n_views} views "
+                        f"{w.width}x{w.height}, M={m}, K_code={sc.views.k_code}, Top-K={k}",
+            "contributions_per_step": nc,
+            "parallelism": "single GPU",
+        },
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * scoup.h -- C ABI of libscoup, the MI355X (gfx950) implementation of the
+ * sparse-code uplift, sparse coefficient render and codebook decode of
+ * "Sparse Code Uplifting for Efficient 3D Language Gaussian Splatting" (SCOUP).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments marked "device" are device pointers owned by the
+ *   caller (HIP allocations on the current device).  Arrays marked "host"
+ *   live in host memory and are only read during the call.
+ * - The library never allocates device memory.  Scratch space comes from the
+ *   caller's workspace `ws` of `ws_bytes` bytes (device, 256-byte aligned),
+ *   sized with the matching *_workspace_bytes query.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *   enqueued on it; every call returns after a single device->host read of a
+ *   small status block on that stream (so results are complete on return).
+ * - Arguments are validated on the host before any launch; a non-OK status
+ *   leaves outputs unspecified and sets a thread-local message that
+ *   scoup_last_error() returns.
+ * - Floating-point results are float32; weight and coefficient accumulation
+ *   is float32 everywhere.  Atomic float additions make bit-level results
+ *   depend on scheduling (sums are order-dependent at the 1e-7 level).
+ */
+#ifndef SCOUP_H_
+#define SCOUP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCOUP_OK = 0,
+  SCOUP_E_ARG = -1,          /* invalid argument (null pointer, bad size, K > M ...) */
+  SCOUP_E_WORKSPACE = -2,    /* workspace too small; see scoup_required_pair_capacity() */
+  SCOUP_E_HIP = -3,          /* a HIP runtime call failed */
+  SCOUP_E_UNSUPPORTED = -4,  /* valid but unsupported configuration */
+  SCOUP_E_DATA = -5          /* bad data found on the device (region id out of range) */
+} scoup_status;
+
+typedef enum { SCOUP_F32 = 0, SCOUP_BF16 = 1, SCOUP_FP8_E4M3 = 2 } scoup_dtype;
+
+/* 3D Gaussians (Sec. 3 "Preliminaries": centre mu, scale s, rotation q,
+ * opacity o; the view-dependent colour is not used).  Structure of arrays,
+ * device, float32:
+ *   means      [n*3]  world-space centres
+ *   log_scales [n*3]  per-axis log standard deviations (activation exp)
+ *   quats      [n*4]  rotation quaternions (w,x,y,z), normalised by the library
+ *   opacities  [n]    activated opacities in (0,1)                          */
+typedef struct {
+  int64_t n;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacities;
+} scoup_gaussians;
+
+/* Pinhole camera (host).  World point X maps to camera point R X + t
+ * (R row-major, world->camera); camera axes +x right, +y down, +z forward;
+ * pixel coordinates (fx x/z + cx, fy y/z + cy); pixel (px,py) is sampled at
+ * its centre (px+0.5, py+0.5).  Points with z <= near_z are culled.         */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float near_z;
+} scoup_camera;
+
+/* The per-view inputs of the uplift (Sec. 4.1-4.2, Algorithm 1).
+ *   cams         host [n_views]
+ *   region_maps  device int32, the H_v*W_v maps of all views concatenated
+ *                row-major; value r >= 0 is a view-local region id, -1 = no
+ *                region (the pixel composites but carries no code)
+ *   map_offsets  host [n_views+1], element offset of each view's map
+ *   region_base  host [n_views+1]; view v has region_base[v+1]-region_base[v]
+ *                regions and region r of view v has global id region_base[v]+r
+ *   code_idx     device int32 [R_total*k_code] atom index of each code slot,
+ *                -1 = empty slot
+ *   code_val     device float32 [R_total*k_code] coefficient of each slot
+ *                (Eq. 4: non-negative, summing to one; not checked)
+ *   k_code       slots per region code (K of Eq. 4)
+ *   m_atoms      codebook size (L of Eq. 4, "M" in this library)          */
+typedef struct {
+  int32_t n_views;
+  const scoup_camera* cams;
+  const int32_t* region_maps;
+  const int64_t* map_offsets;
+  const int64_t* region_base;
+  const int32_t* code_idx;
+  const float* code_val;
+  int32_t k_code;
+  int32_t m_atoms;
+} scoup_views;
+
+/* Workspace bytes for scoup_uplift / scoup_uplift_accumulate given a capacity
+ * for (Gaussian, 16x16-tile) pairs of one view.  A capacity of 0 picks a
+ * default of 8 pairs per Gaussian.                                           */
+size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* views,
+                                    int64_t pair_capacity);
+
+/* After SCOUP_E_WORKSPACE: the pair capacity the failed call needed (the
+ * largest per-view pair count it saw).  Thread-local.                       */
+int64_t scoup_required_pair_capacity(void);
+
+/* Weighted sparse accumulation, Eq. 5 without the normaliser Z_i (Eq. 6
+ * subsumes it) and the loops of Algorithm 1:
+ *   acc[i*m + j] += sum over views v, pixels p with region r >= 0,
+ *                   Gaussians i in N_{v,p}, code slots (j, c) of region r:
+ *                   c * e_i(v,p)
+ * with e_i(v,p) = alpha_i T_i the front-to-back blending weight of Eq. 2 under
+ * the 3DGS numerics (alpha = min(0.99, o G2D); alpha < 1/255 skipped; the
+ * Gaussian that would take T below 1e-4 is excluded and ends the pixel),
+ * G2D the EWA splat with +0.3 px^2 dilation and the 1.3 tan(fov/2) Jacobian
+ * clamp, depth order by float32(view depth) with ties to the lower index.
+ *   acc        device float32 [n*m], row-major (Gaussian-major)
+ *   accumulate 0: acc is overwritten (zeroed first); 1: results are added to
+ *              the values already in acc (resume over a further view set)
+ *   n_contrib  device uint64 [1] or NULL; receives (+=) the number of
+ *              Gaussian-pixel contributions (terms e > 0) composited
+ * Returns SCOUP_E_WORKSPACE if a view's pair count exceeds the capacity the
+ * workspace was sized for (acc is then incomplete; call again with a larger
+ * workspace), SCOUP_E_DATA if a region id is >= the view's region count.    */
+scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views* views,
+                                     float* acc, int32_t accumulate,
+                                     void* ws, size_t ws_bytes,
+                                     unsigned long long* n_contrib, void* stream);
+
+/* Top-K filter and L1 normalisation of Eq. 6, per row of acc (n rows of m):
+ * entries ranked by (value descending, index ascending); the first k strictly
+ * positive ones are kept and divided by their sum; missing entries are padded
+ * with (idx -1, val 0); an all-zero row is all padding (Algorithm 1 skips it).
+ *   acc      device float32 [n*m]   (read only)
+ *   idx      device int32   [n*k]   atom indices in rank order
+ *   val      device float32 [n*k]   normalised coefficients
+ * Requires 1 <= k <= m <= 4096.                                             */
+scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k,
+                        int32_t* idx, float* val, void* stream);
+
+/* The full uplift of Algorithm 1: acc is zeroed, accumulated over every view
+ * (scoup_uplift_accumulate) and reduced to k coefficients per Gaussian
+ * (scoup_topk).  Arguments as above.                                        */
+scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* views, int32_t k,
+                          float* acc, int32_t* topk_idx, float* topk_val,
+                          void* ws, size_t ws_bytes, unsigned long long* n_contrib,
+                          void* stream);
+
+/* Optional per-stage kernel timing with HIP events recorded on the call's
+ * stream around every launch (off by default; costs one event pair per
+ * launch).  scoup_stage_timing(1) enables and resets the counters,
+ * scoup_stage_timing(0) disables them.  scoup_stage_stats returns, for stage
+ * id `stage`, the summed kernel time in milliseconds and the launch count
+ * accumulated by completed calls since the last reset; it returns 0 on
+ * success and -1 for an unknown stage.  Stage ids:
+ *   0 project  1 tile scan  2 emit  3 dense-tile sort  4 composite+accumulate
+ *   5 top-k    6 render     7 decode  8 render backward  9 backward GEMMs
+ * Process-wide state; not meant for concurrent calls from several threads. */
+void scoup_stage_timing(int32_t enable);
+int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char* scoup_last_error(void);
+
+/* Library version string. */
+const char* scoup_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCOUP_H_ */

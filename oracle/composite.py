@@ -89,6 +89,13 @@ def composite_view(proj: Projection, width: int, height: int, band: int = 32,
                    eps_T: float = 1e-4, track_marginal: bool = True) -> ViewWeights:
     """Composite every pixel (or those in ``pixel_mask``) of one view."""
     ids = np.flatnonzero(proj.visible)
+    if pixel_mask is not None:
+        # keep only Gaussians whose box holds a pixel in scope (summed-area table)
+        sat = np.zeros((height + 1, width + 1), np.int64)
+        sat[1:, 1:] = pixel_mask.reshape(height, width).cumsum(0).cumsum(1)
+        x0, x1, y0, y1 = (proj.box[ids, k] for k in range(4))
+        tot = sat[y1 + 1, x1 + 1] - sat[y0, x1 + 1] - sat[y1 + 1, x0] + sat[y0, x0]
+        ids = ids[tot > 0]
     t_final = np.ones(width * height)
     out_g, out_p, out_e = [], [], []
     marginal = {}

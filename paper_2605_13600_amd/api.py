@@ -1,0 +1,189 @@
+"""Torch-facing wrappers of the libscoup C ABI.
+
+torch supplies device memory and the stream; every arithmetic step runs in
+libscoup's HIP kernels.  Inputs are torch tensors already on the GPU (or
+host arrays that these helpers copy there once).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class ScoupError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libscoup status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int) -> None:
+    if status != L.OK:
+        raise ScoupError(status, L.load().scoup_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+@dataclasses.dataclass
+class DeviceGaussians:
+    """Gaussians on the GPU: means (N,3), log_scales (N,3), quats (N,4) w-first,
+    opacities (N,), all float32 contiguous."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def struct(self) -> L.Gaussians:
+        return L.Gaussians(self.n, _ptr(self.means), _ptr(self.log_scales), _ptr(self.quats),
+                           _ptr(self.opacities))
+
+
+def camera_struct(cam) -> L.Camera:
+    """scoup_camera from any object with R, t, fx, fy, cx, cy, width, height, near."""
+    c = L.Camera()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).reshape(9)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.near_z = float(getattr(cam, "near", 0.2))
+    return c
+
+
+@dataclasses.dataclass
+class DeviceViews:
+    """Per-view inputs of the uplift with the region maps and codes on the GPU."""
+    cams: Sequence
+    region_maps: torch.Tensor      # int32, all views concatenated
+    map_offsets: np.ndarray        # int64 (V+1,)
+    region_base: np.ndarray        # int64 (V+1,)
+    code_idx: torch.Tensor         # int32 (R_total, k_code)
+    code_val: torch.Tensor         # float32 (R_total, k_code)
+    m_atoms: int
+
+    def __post_init__(self):
+        self._cams = (L.Camera * max(1, len(self.cams)))(*[camera_struct(c) for c in self.cams])
+        self._moff = np.ascontiguousarray(self.map_offsets, np.int64)
+        self._rbase = np.ascontiguousarray(self.region_base, np.int64)
+
+    @property
+    def n_views(self) -> int:
+        return len(self.cams)
+
+    @property
+    def k_code(self) -> int:
+        return int(self.code_idx.shape[1])
+
+    def struct(self) -> L.Views:
+        return L.Views(self.n_views, self._cams, _ptr(self.region_maps),
+                       self._moff.ctypes.data_as(C.POINTER(C.c_int64)),
+                       self._rbase.ctypes.data_as(C.POINTER(C.c_int64)),
+                       _ptr(self.code_idx), _ptr(self.code_val), self.k_code, int(self.m_atoms))
+
+
+def gaussians_to_device(g, device="cuda") -> DeviceGaussians:
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+    return DeviceGaussians(f(g.means), f(g.log_scales), f(g.quats), f(g.opacities))
+
+
+def views_to_device(v, device="cuda") -> DeviceViews:
+    """Copy an object with cameras, region_maps, region_base, code_idx, code_val,
+    m_atoms (host arrays) to the GPU."""
+    maps = [np.ascontiguousarray(m, np.int32).reshape(-1) for m in v.region_maps]
+    off = np.zeros(len(maps) + 1, np.int64)
+    off[1:] = np.cumsum([m.size for m in maps])
+    rm = torch.from_numpy(np.concatenate(maps) if maps else np.zeros(1, np.int32)).to(device)
+    ci = torch.as_tensor(np.ascontiguousarray(v.code_idx, np.int32)).to(device)
+    cv = torch.as_tensor(np.ascontiguousarray(v.code_val, np.float32)).to(device)
+    return DeviceViews(list(v.cameras), rm, off, np.asarray(v.region_base, np.int64), ci, cv,
+                       int(v.m_atoms))
+
+
+_capacity_cache = {}
+
+
+class Workspace:
+    """Grow-only device workspace for the uplift calls."""
+
+    def __init__(self, device="cuda"):
+        self.buf = None
+        self.device = device
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _workspace(device) -> Workspace:
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def uplift_accumulate(g: DeviceGaussians, views: DeviceViews, acc: Optional[torch.Tensor] = None,
+                      accumulate: bool = False, stream=None, workspace: Optional[Workspace] = None,
+                      pair_capacity: int = 0):
+    """acc (N, M) float32 += Eq. 5 over every view (zeroed first unless ``accumulate``).
+    Returns (acc, n_contrib)."""
+    lib = L.load()
+    dev = g.means.device
+    if acc is None:
+        acc = torch.empty((g.n, views.m_atoms), dtype=torch.float32, device=dev)
+    ws = workspace or _workspace(dev)
+    gs, vs = g.struct(), views.struct()
+    key = (g.n, views.n_views, tuple(views._moff.tolist()[-1:]))
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        nbytes = lib.scoup_uplift_workspace_bytes(g.n, C.byref(vs), cap)
+        buf = ws.get(nbytes)
+        cnt.zero_()
+        st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), _ptr(acc), int(accumulate),
+                                         _ptr(buf), buf.numel(), _ptr(cnt), _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return acc, int(cnt.item())
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+def topk(acc: torch.Tensor, k: int, stream=None):
+    """Eq. 6 per row of acc (N, M): (idx int32 (N,k), val float32 (N,k))."""
+    lib = L.load()
+    n, m = acc.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=acc.device)
+    val = torch.empty((n, k), dtype=torch.float32, device=acc.device)
+    _check(lib.scoup_topk(_ptr(acc), n, m, k, _ptr(idx), _ptr(val), _stream(stream)))
+    return idx, val
+
+
+def uplift(g: DeviceGaussians, views: DeviceViews, k: int, stream=None, workspace=None,
+           pair_capacity: int = 0):
+    """Algorithm 1: accumulate over all views, then Top-K.  Returns
+    (idx (N,k) int32, val (N,k) float32, acc (N,M) float32, n_contrib)."""
+    acc, nc = uplift_accumulate(g, views, stream=stream, workspace=workspace,
+                                pair_capacity=pair_capacity)
+    idx, val = topk(acc, k, stream=stream)
+    return idx, val, acc, nc
