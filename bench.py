@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes as C
+from ctypes import byref as C_byref, c_double as C_double, c_int64 as C_int64
 import json
 import os
 import sys
@@ -69,6 +70,60 @@ def cpu_baseline(sc, rows=192):
                        f"(FP64 NumPy, one process)")
 
 
+def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
+    """Render (Eq. 7) + decode (Eq. 8) of the 1M-Gaussian scene with synthetic
+    Top-8 over M=256, codebook 256x512, on the first ``n_views`` of 100 orbit
+    views at 1440x1080; FP32, BF16 and FP8 decode inputs."""
+    m, d, k = 256, 512, 8
+    cams = sg.orbit_cameras(2002, 100, 12.0, 1.0, 4.0, 1.0, 0.5, 1440, 1080, 60.0)[:n_views]
+    ti, tv = sg.random_topk(2003, gaussians.n, m, k)
+    cb = sg.random_codebook(2004, m, d)
+    dg = P.gaussians_to_device(gaussians)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    dC = torch.from_numpy(cb).cuda()
+    px = 1440 * 1080
+    res = {"workload": f"render+decode: {gaussians.n} Gaussians, Top-{k} over M={m}, codebook {m}x{d}, "
+                       f"{n_views} views 1440x1080", "views": n_views}
+    peak = {"f32": (157.3, "TFLOP/s"), "bf16": (2500.0, "TFLOP/s"), "fp8": (5000.0, "TFLOP/s")}
+    in_b = {"f32": 4, "bf16": 2, "fp8": 1}
+    for dt in ("f32", "bf16", "fp8"):
+        out_dt = "f32" if dt == "f32" else "bf16"
+        W, _, nc, scl = P.render_coeff(dg, dti, dtv, cams[0], m, dtype=dt)
+        F = P.decode(W, dC, dt, coeff_scale=scl, out_dtype=out_dt)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for cam in cams:
+            W, _, nc, scl = P.render_coeff(dg, dti, dtv, cam, m, dtype=dt, want_t_final=False)
+            F = P.decode(W, dC, dt, coeff_scale=scl, out_dtype=out_dt)
+        torch.cuda.synchronize()
+        t_rd = time.perf_counter() - t0
+        # decode alone, with HIP events on the launch stream
+        lib.scoup_stage_timing(1)
+        for _ in range(n_views):
+            F = P.decode(W, dC, dt, coeff_scale=scl, out_dtype=out_dt)
+        tot, cnt = C_double(), C_int64()
+        lib.scoup_stage_stats(7, C_byref(tot), C_byref(cnt))
+        lib.scoup_stage_timing(0)
+        dec_us = tot.value * 1e3 / max(1, cnt.value)
+        flops = 2.0 * px * m * d
+        bytes_ = px * (m * in_b[dt] + d * (4 if out_dt == "f32" else 2))
+        tf = flops / (dec_us * 1e-6) / 1e12
+        gbs = bytes_ / (dec_us * 1e-6) / 1e9
+        pk, _ = peak[dt]
+        res[dt] = {
+            "render_decode_mpix_s": round(px * n_views / t_rd / 1e6, 2),
+            "decode_mpix_s": round(px / (dec_us * 1e-6) / 1e6, 2),
+            "decode_avg_us": round(dec_us, 2),
+            "decode_tflops": round(tf, 2), "decode_mfma_frac": round(tf / pk, 4),
+            "decode_hbm_gbs": round(gbs, 1), "decode_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "decode_arith_intensity": round(flops / bytes_, 1),
+            "decode_mfma_ceiling": round(min(1.0, (flops / bytes_) / (pk * 1e12 / (HBM_PEAK_GBS * 1e9))), 4),
+            "contributions_per_view": nc,
+        }
+        log(f"render+decode {dt}: {res[dt]}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +132,8 @@ def main():
     ap.add_argument("--workload", default="scene", choices=["scene", "tiny", "large"])
     ap.add_argument("--views", type=int, default=None, help="use only the first views (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--render-views", type=int, default=100,
+                    help="views of the 1440x1080 render workload to time (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -147,6 +204,10 @@ def main():
                     per_launch=f"{nc / sc.views.n_views:.4g} contributions x "
                                f"{flops_per_contribution(sc.views.k_code)} flops")
 
+    render = None
+    if args.render_views > 0:
+        render = bench_render_decode(args.render_views, sc.gaussians, lib, P, sg, torch, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the CPU sample ...")
@@ -176,6 +237,7 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "render_decode": render,
     }
     print(json.dumps(out), flush=True)
 

@@ -147,6 +147,70 @@ scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* views, in
                           void* ws, size_t ws_bytes, unsigned long long* n_contrib,
                           void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Sparse coefficient render (Eq. 7), decode (Eq. 8) and their backward
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for scoup_render_coeff on `cam` given a capacity for
+ * (Gaussian, 8x8-block) pairs; 0 picks 16 pairs per Gaussian.               */
+size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam,
+                                    int64_t pair_capacity);
+
+/* Eq. 7 for one camera: coeff_map[p*m + j] = coeff_scale * sum over Gaussians i
+ * in N_{v,p} (same compositing as the uplift) of e_i(v,p) * topk_val[i*k + s]
+ * for every slot s with topk_idx[i*k + s] == j (slots with index -1 are
+ * skipped).  Accumulation is float32; the map is written once per pixel in
+ * coeff_dtype (F32, BF16 round-to-nearest-even, or FP8 E4M3 saturating; use
+ * coeff_scale to place FP8 values in range, e.g. 256 since coefficients are
+ * at most 1).
+ *   topk_idx   device int32   [n*k], 1 <= k <= 16, indices < m_atoms (else SCOUP_E_DATA)
+ *   topk_val   device float32 [n*k]
+ *   coeff_map  device [H*W*m_atoms] of coeff_dtype, pixel-major (y*W + x)
+ *   t_final    device float32 [H*W] transmittance left at each pixel, or NULL
+ *   n_contrib  device uint64 [1] (+=) contributions composited, or NULL
+ * Requires 1 <= m_atoms <= 1024.                                             */
+scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx,
+                                const float* topk_val, int32_t k, int32_t m_atoms,
+                                const scoup_camera* cam, void* coeff_map, scoup_dtype coeff_dtype,
+                                float coeff_scale, float* t_final, void* ws, size_t ws_bytes,
+                                unsigned long long* n_contrib, void* stream);
+
+/* Workspace bytes for scoup_decode (the codebook converted to in_dtype and
+ * arranged in MFMA operand order).                                          */
+size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in_dtype);
+
+/* Eq. 8: features[p*dim + d] = (1/coeff_scale) sum_j coeff[p*m + j] * codebook[j*dim + d]
+ * on MFMA with float32 accumulation.  The float32 codebook is converted to
+ * in_dtype inside the call (FP8 with a power-of-two per-tensor scale that is
+ * divided out again).  out_dtype is F32 or BF16 (round to nearest even).
+ *   coeff     device [n_pixels*m_atoms] of in_dtype
+ *   codebook  device float32 [m_atoms*dim]
+ *   features  device [n_pixels*dim] of out_dtype
+ * Requires 1 <= m_atoms <= 4096 and 1 <= dim <= 1024.                       */
+scoup_status scoup_decode(const void* coeff, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                          int32_t m_atoms, const float* codebook, int32_t dim, void* features,
+                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for scoup_render_backward. */
+size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam,
+                                             int32_t m_atoms, int32_t dim, int64_t pair_capacity);
+
+/* Backward of render + decode (float32) for a loss with gradient
+ * G = dL/dfeatures on one camera:
+ *   grad_codebook[j*dim + d] += sum_p coeff_map[p*m + j] G[p*dim + d]
+ *   grad_topk_val[i*k + s]   += sum_p e_i(v,p) (G(p) C^T)[topk_idx[i*k + s]]
+ * Indices and geometry receive no gradient.  coeff_map is the float32 map of
+ * scoup_render_coeff (coeff_scale 1) for the same inputs.
+ *   grad_features  device float32 [H*W*dim]
+ *   grad_topk_val  device float32 [n*k]       (accumulated)
+ *   grad_codebook  device float32 [m_atoms*dim] (accumulated)              */
+scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk_idx,
+                                   const float* topk_val, int32_t k, int32_t m_atoms,
+                                   const scoup_camera* cam, const float* coeff_map,
+                                   const float* codebook, int32_t dim, const float* grad_features,
+                                   float* grad_topk_val, float* grad_codebook, void* ws,
+                                   size_t ws_bytes, void* stream);
+
 /* Optional per-stage kernel timing with HIP events recorded on the call's
  * stream around every launch (off by default; costs one event pair per
  * launch).  scoup_stage_timing(1) enables and resets the counters,

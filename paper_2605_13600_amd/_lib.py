@@ -39,6 +39,18 @@ SIGNATURES = {
                              C.c_void_p]),
     "scoup_uplift": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_int32, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "scoup_render_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Camera), C.c_int64]),
+    "scoup_render_coeff": (C.c_int, [C.POINTER(Gaussians), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.POINTER(Camera), C.c_void_p, C.c_int, C.c_float, C.c_void_p,
+                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "scoup_decode_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int]),
+    "scoup_decode": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_int32, C.c_void_p, C.c_int32,
+                               C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "scoup_render_backward_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Camera), C.c_int32, C.c_int32,
+                                                           C.c_int64]),
+    "scoup_render_backward": (C.c_int, [C.POINTER(Gaussians), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(Camera), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "scoup_stage_timing": (None, [C.c_int32]),
     "scoup_stage_stats": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "scoup_last_error": (C.c_char_p, []),

@@ -187,3 +187,124 @@ def uplift(g: DeviceGaussians, views: DeviceViews, k: int, stream=None, workspac
                                 pair_capacity=pair_capacity)
     idx, val = topk(acc, k, stream=stream)
     return idx, val, acc, nc
+
+
+_DT = {"f32": L.F32, "bf16": L.BF16, "fp8": L.FP8_E4M3}
+_TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "fp8": torch.uint8}
+FP8_COEFF_SCALE = 256.0   # rendered coefficients are <= 1; x256 keeps them inside E4M3's range
+
+
+def render_coeff(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, cam, m_atoms: int,
+                 dtype: str = "f32", scale: Optional[float] = None, want_t_final: bool = True,
+                 stream=None, workspace: Optional[Workspace] = None, pair_capacity: int = 0):
+    """Eq. 7 for one camera: coefficient map (H, W, M) in ``dtype`` (``f32``,
+    ``bf16`` or ``fp8`` = E4M3 bytes scaled by ``scale``), the final
+    transmittance (H, W) and the contribution count."""
+    lib = L.load()
+    dev = g.means.device
+    c = camera_struct(cam)
+    H, W = int(cam.height), int(cam.width)
+    if scale is None:
+        scale = FP8_COEFF_SCALE if dtype == "fp8" else 1.0
+    out = torch.empty((H, W, m_atoms), dtype=_TORCH_DT[dtype], device=dev)
+    tf = torch.empty((H, W), dtype=torch.float32, device=dev) if want_t_final else None
+    ws = workspace or _workspace(dev)
+    gs = g.struct()
+    k = int(topk_idx.shape[1])
+    key = ("render", g.n, W, H)
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        nbytes = lib.scoup_render_workspace_bytes(g.n, C.byref(c), cap)
+        buf = ws.get(nbytes)
+        cnt.zero_()
+        st = lib.scoup_render_coeff(C.byref(gs), _ptr(topk_idx), _ptr(topk_val), k, m_atoms, C.byref(c),
+                                    _ptr(out), _DT[dtype], float(scale), _ptr(tf), _ptr(buf), buf.numel(),
+                                    _ptr(cnt), _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return out, tf, int(cnt.item()), float(scale)
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+def decode(coeff: torch.Tensor, codebook: torch.Tensor, in_dtype: str = "bf16", coeff_scale: float = 1.0,
+           out_dtype: str = "bf16", stream=None, workspace: Optional[Workspace] = None) -> torch.Tensor:
+    """Eq. 8: features = coeff @ codebook on MFMA.  ``coeff`` is (..., M) in
+    ``in_dtype`` storage (float32, bfloat16 or E4M3 bytes scaled by
+    ``coeff_scale``); ``codebook`` is the float32 (M, D) codebook, converted
+    to ``in_dtype`` by the library.  Returns (..., D) in ``out_dtype``."""
+    lib = L.load()
+    m, d = codebook.shape
+    P = coeff.numel() // m
+    out = torch.empty((*coeff.shape[:-1], d), dtype=_TORCH_DT[out_dtype], device=coeff.device)
+    ws = workspace or Workspace(coeff.device)
+    buf = ws.get(lib.scoup_decode_workspace_bytes(m, d, _DT[in_dtype]))
+    _check(lib.scoup_decode(_ptr(coeff), _DT[in_dtype], float(coeff_scale), P, m, _ptr(codebook), d,
+                            _ptr(out), _DT[out_dtype], _ptr(buf), buf.numel(), _stream(stream)))
+    return out
+
+
+def render_backward(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, cam,
+                    coeff_map: torch.Tensor, codebook: torch.Tensor, grad_features: torch.Tensor,
+                    grad_topk_val: Optional[torch.Tensor] = None, grad_codebook: Optional[torch.Tensor] = None,
+                    stream=None, workspace: Optional[Workspace] = None, pair_capacity: int = 0):
+    """Backward of render + decode for one camera (float32).  Accumulates into
+    (and returns) grad_topk_val (N, K) and grad_codebook (M, D)."""
+    lib = L.load()
+    dev = g.means.device
+    m, d = codebook.shape
+    k = int(topk_idx.shape[1])
+    if grad_topk_val is None:
+        grad_topk_val = torch.zeros_like(topk_val)
+    if grad_codebook is None:
+        grad_codebook = torch.zeros_like(codebook)
+    c = camera_struct(cam)
+    ws = workspace or _workspace(dev)
+    gs = g.struct()
+    key = ("render", g.n, int(cam.width), int(cam.height))
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    for _ in range(4):
+        nbytes = lib.scoup_render_backward_workspace_bytes(g.n, C.byref(c), m, d, cap)
+        buf = ws.get(nbytes)
+        st = lib.scoup_render_backward(C.byref(gs), _ptr(topk_idx), _ptr(topk_val), k, m, C.byref(c),
+                                       _ptr(coeff_map), _ptr(codebook), d, _ptr(grad_features),
+                                       _ptr(grad_topk_val), _ptr(grad_codebook), _ptr(buf), buf.numel(),
+                                       _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return grad_topk_val, grad_codebook
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+class RenderDecode(torch.autograd.Function):
+    """features (H, W, D) float32 = decode(render(topk, cam), codebook), with
+    gradients for ``topk_val`` and ``codebook`` from libscoup's backward.
+    Also returns the final transmittance (H, W) (not differentiable)."""
+
+    @staticmethod
+    def forward(ctx, topk_val, codebook, g, topk_idx, cam):
+        m = int(codebook.shape[0])
+        W, tf, _, _ = render_coeff(g, topk_idx, topk_val, cam, m, dtype="f32")
+        F = decode(W, codebook, "f32", out_dtype="f32")
+        ctx.save_for_backward(topk_val, codebook, topk_idx, W)
+        ctx.g, ctx.cam = g, cam
+        ctx.mark_non_differentiable(tf)
+        return F, tf
+
+    @staticmethod
+    def backward(ctx, dF, dtf):
+        topk_val, codebook, topk_idx, W = ctx.saved_tensors
+        gv, gc = render_backward(ctx.g, topk_idx, topk_val, ctx.cam, W, codebook, dF.contiguous())
+        return gv, gc, None, None, None
+
+
+def render_decode(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, codebook: torch.Tensor,
+                  cam):
+    """Differentiable render + decode (float32): returns (features, t_final)."""
+    return RenderDecode.apply(topk_val, codebook, g, topk_idx, cam)

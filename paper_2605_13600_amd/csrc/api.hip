@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -37,22 +38,55 @@ struct UpliftLayout {
   int max_tiles;
 };
 
-int tiles_of(int w, int h) { return ((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile); }
+int tiles_of(int w, int h, int shift = 4) {
+  const int t = 1 << shift;
+  return ((w + t - 1) >> shift) * ((h + t - 1) >> shift);
+}
 
-UpliftLayout uplift_layout(int64_t n, const scoup_views* v) {
+UpliftLayout bin_layout(int64_t n, int max_tiles) {
   UpliftLayout L{};
-  int mt = 1;
-  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height));
-  L.max_tiles = mt;
+  L.max_tiles = std::max(1, max_tiles);
   size_t off = 0;
   L.status = off; off = align256(off + sizeof(Status));
   L.splats = off; off = align256(off + sizeof(GSplat) * (size_t)std::max<int64_t>(n, 1));
-  L.tile_count = off; off = align256(off + 4 * (size_t)mt);
-  L.tile_cursor = off; off = align256(off + 4 * (size_t)mt);
-  L.tile_start = off; off = align256(off + 4 * (size_t)(mt + 1));
+  L.tile_count = off; off = align256(off + 4 * (size_t)L.max_tiles);
+  L.tile_cursor = off; off = align256(off + 4 * (size_t)L.max_tiles);
+  L.tile_start = off; off = align256(off + 4 * (size_t)(L.max_tiles + 1));
   L.keys = off;
   L.fixed = off;
   return L;
+}
+
+UpliftLayout uplift_layout(int64_t n, const scoup_views* v) {
+  int mt = 1;
+  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height));
+  return bin_layout(n, mt);
+}
+
+void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const UpliftLayout& L, long long capacity,
+              int shift, int sort_cap) {
+  b.means = g->means; b.log_scales = g->log_scales; b.quats = g->quats; b.opacities = g->opacities;
+  b.n = g->n;
+  b.tile_shift = shift;
+  b.sort_cap = sort_cap;
+  b.splats = reinterpret_cast<GSplat*>(base + L.splats);
+  b.tile_count = reinterpret_cast<unsigned int*>(base + L.tile_count);
+  b.tile_cursor = reinterpret_cast<unsigned int*>(base + L.tile_cursor);
+  b.tile_start = reinterpret_cast<unsigned int*>(base + L.tile_start);
+  b.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
+  b.capacity = capacity;
+  b.status = reinterpret_cast<Status*>(base + L.status);
+}
+
+std::once_flag g_lds_once;
+hipError_t g_lds_err = hipSuccess;
+hipError_t ensure_lds_limits() {
+  std::call_once(g_lds_once, [] {
+    g_lds_err = render_set_lds_limits();
+    if (g_lds_err == hipSuccess) g_lds_err = decode_set_lds_limits();
+    if (g_lds_err == hipSuccess) g_lds_err = render_bwd_set_lds_limits();
+  });
+  return g_lds_err;
 }
 
 scoup_status check_gaussians(const scoup_gaussians* g) {
@@ -212,23 +246,16 @@ scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views
   if (!accumulate && acc_bytes) HIP_TRY(hipMemsetAsync(acc, 0, acc_bytes, s));
 
   UpliftViewArgs a{};
-  a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.opacities = g->opacities;
-  a.n = g->n;
-  a.splats = reinterpret_cast<GSplat*>(base + L.splats);
-  a.tile_count = reinterpret_cast<unsigned int*>(base + L.tile_count);
-  a.tile_cursor = reinterpret_cast<unsigned int*>(base + L.tile_cursor);
-  a.tile_start = reinterpret_cast<unsigned int*>(base + L.tile_start);
-  a.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
-  a.capacity = capacity;
+  BinArgs& b = a.bin;
+  fill_bin(b, g, base, L, capacity, 4, kSortCap);
   a.code_idx = v->code_idx; a.code_val = v->code_val;
   a.k_code = v->k_code; a.m_atoms = v->m_atoms;
   a.acc = acc;
-  a.status = status;
   for (int i = 0; i < v->n_views; ++i) {
     const scoup_camera& c = v->cams[i];
-    a.cam = to_dev(c);
-    a.tiles_x = (c.width + kTile - 1) / kTile;
-    a.n_tiles = tiles_of(c.width, c.height);
+    b.cam = to_dev(c);
+    b.tiles_x = (c.width + kTile - 1) / kTile;
+    b.n_tiles = tiles_of(c.width, c.height);
     a.rmap = v->region_maps + v->map_offsets[i];
     a.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
     a.region_base = v->region_base[i];
@@ -273,6 +300,181 @@ scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* v, int32_
   scoup_status st = scoup_uplift_accumulate(g, v, acc, 0, ws, ws_bytes, n_contrib, stream);
   if (st != SCOUP_OK) return st;
   return scoup_topk(acc, g->n, v->m_atoms, k, topk_idx, topk_val, stream);
+}
+
+size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int64_t pair_capacity) {
+  if (!cam || n_gaussians < 0) return 0;
+  UpliftLayout L = bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3));
+  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(16 * n_gaussians, 1 << 16);
+  return L.fixed + align256(8 * (size_t)pair_capacity);
+}
+
+scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
+                                int32_t k, int32_t m_atoms, const scoup_camera* cam, void* coeff_map,
+                                scoup_dtype coeff_dtype, float coeff_scale, float* t_final, void* ws,
+                                size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  scoup_status st = check_gaussians(g);
+  if (st != SCOUP_OK) return st;
+  if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
+  if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
+  if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
+  if (m_atoms < 1 || m_atoms > 1024) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 1024]");
+  if (coeff_dtype != SCOUP_F32 && coeff_dtype != SCOUP_BF16 && coeff_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown coefficient dtype");
+  if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
+  if (!coeff_map) return fail(SCOUP_E_ARG, "coeff_map is NULL");
+  if (g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  HIP_TRY(ensure_lds_limits());
+  const int shift = 3;
+  const UpliftLayout L = bin_layout(g->n, tiles_of(cam->width, cam->height, shift));
+  if (ws_bytes < L.fixed + 8 * 1024) {
+    g_required_pairs = std::max<int64_t>(16 * g->n, 1 << 16);
+    return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
+  }
+  long long capacity = std::min<long long>((long long)((ws_bytes - L.fixed) / 8), 0x7fffffffLL);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  RenderViewArgs a{};
+  fill_bin(a.bin, g, base, L, capacity, shift, 0);
+  const int sort_cap = [&] { int c = 1; while (2 * c <= 32 * (m_atoms + 1)) c *= 2; return c; }();
+  a.bin.sort_cap = sort_cap;
+  a.bin.cam = to_dev(*cam);
+  a.bin.tiles_x = (cam->width + 7) / 8;
+  a.bin.n_tiles = tiles_of(cam->width, cam->height, shift);
+  a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
+  a.out_dtype = coeff_dtype; a.out = coeff_map; a.out_scale = coeff_scale; a.t_final = t_final;
+  Status* status = a.bin.status;
+  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  HIP_TRY(hipMemsetAsync(base + L.tile_count, 0, 4 * (size_t)L.max_tiles, s));
+  HIP_TRY(launch_render_view(a, s));
+  if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
+  Status h{};
+  HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  if (h.any_overflow) {
+    g_required_pairs = (int64_t)h.max_pairs;
+    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(capacity) + " exceeded; need " +
+                                       std::to_string(h.max_pairs));
+  }
+  if (h.data_error & 4u) return fail(SCOUP_E_DATA, "a Top-K atom index is >= m_atoms");
+  return SCOUP_OK;
+}
+
+size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in_dtype) {
+  if (m_atoms < 1 || dim < 1) return 0;
+  return 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));
+}
+
+scoup_status scoup_decode(const void* coeff_map, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                          int32_t m_atoms, const float* codebook, int32_t dim, void* features,
+                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown input dtype");
+  if (out_dtype != SCOUP_F32 && out_dtype != SCOUP_BF16) return fail(SCOUP_E_ARG, "output dtype must be F32 or BF16");
+  if (n_pixels < 0) return fail(SCOUP_E_ARG, "n_pixels < 0");
+  if (m_atoms < 1 || m_atoms > 4096) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 4096]");
+  if (dim < 1 || dim > 1024) return fail(SCOUP_E_UNSUPPORTED, "dim must be in [1, 1024]");
+  if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
+  if (!codebook || !features || (n_pixels > 0 && !coeff_map)) return fail(SCOUP_E_ARG, "a decode array is NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  if (ws_bytes < scoup_decode_workspace_bytes(m_atoms, dim, in_dtype))
+    return fail(SCOUP_E_WORKSPACE, "decode workspace too small");
+  HIP_TRY(ensure_lds_limits());
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* scale = reinterpret_cast<float*>(base);
+  void* prep = base + 256;
+  HIP_TRY(launch_prep_codebook(codebook, m_atoms, dim, in_dtype, prep, scale, s, 0));
+  DecodeArgs a{};
+  a.coeff = coeff_map; a.P = n_pixels; a.m = m_atoms; a.d = dim; a.kpad = decode_kpad(m_atoms, in_dtype);
+  a.in_dtype = in_dtype; a.out_dtype = out_dtype; a.codebook_prep = prep;
+  a.cb_scale = in_dtype == SCOUP_FP8_E4M3 ? scale : nullptr;
+  a.out_mul = 1.0f / coeff_scale;
+  a.out = features;
+  HIP_TRY(launch_decode(a, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  return SCOUP_OK;
+}
+
+size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t m_atoms,
+                                              int32_t dim, int64_t pair_capacity) {
+  if (!cam || n_gaussians < 0 || m_atoms < 1 || dim < 1) return 0;
+  const size_t P = (size_t)cam->width * cam->height;
+  const size_t pre = align256(decode_codebook_bytes(dim, m_atoms, SCOUP_F32)) + align256(4 * P * m_atoms);
+  return pre + scoup_render_workspace_bytes(n_gaussians, cam, pair_capacity);
+}
+
+scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
+                                   int32_t k, int32_t m_atoms, const scoup_camera* cam, const float* coeff_map,
+                                   const float* codebook, int32_t dim, const float* grad_features,
+                                   float* grad_topk_val, float* grad_codebook, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  g_err.clear();
+  scoup_status st = check_gaussians(g);
+  if (st != SCOUP_OK) return st;
+  if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
+  if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
+  if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
+  if (m_atoms < 1 || m_atoms > 1024) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 1024]");
+  if (dim < 1 || dim > 4096) return fail(SCOUP_E_ARG, "dim must be in [1, 4096]");
+  if (!coeff_map || !codebook || !grad_features || !grad_codebook)
+    return fail(SCOUP_E_ARG, "a backward array is NULL");
+  if (g->n > 0 && (!topk_idx || !topk_val || !grad_topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  HIP_TRY(ensure_lds_limits());
+  const long long P = (long long)cam->width * cam->height;
+  const size_t prep_b = align256(decode_codebook_bytes(dim, m_atoms, SCOUP_F32));
+  const size_t dw_b = align256(4 * (size_t)P * m_atoms);
+  const int shift = 3;
+  const UpliftLayout L = bin_layout(g->n, tiles_of(cam->width, cam->height, shift));
+  if (ws_bytes < prep_b + dw_b + L.fixed + 8 * 1024) {
+    g_required_pairs = std::max<int64_t>(16 * g->n, 1 << 16);
+    return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
+  }
+  char* base = static_cast<char*>(ws);
+  void* prep = base;
+  float* dW = reinterpret_cast<float*>(base + prep_b);
+  char* bbase = base + prep_b + dw_b;
+  long long capacity =
+      std::min<long long>((long long)((ws_bytes - prep_b - dw_b - L.fixed) / 8), 0x7fffffffLL);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // dW = G C^T : K = dim, N = m_atoms, B(k, n) = C[n * dim + k]
+  HIP_TRY(launch_prep_codebook(codebook, dim, m_atoms, SCOUP_F32, prep, nullptr, s, 1));
+  DecodeArgs d{};
+  d.coeff = grad_features; d.P = P; d.m = dim; d.d = m_atoms; d.kpad = decode_kpad(dim, SCOUP_F32);
+  d.in_dtype = SCOUP_F32; d.out_dtype = SCOUP_F32; d.codebook_prep = prep; d.cb_scale = nullptr;
+  d.out_mul = 1.0f; d.out = dW; d.ldo = m_atoms;
+  HIP_TRY(launch_decode(d, s, kStBwdGemm));
+  HIP_TRY(launch_gemm_at_b(coeff_map, grad_features, P, m_atoms, dim, grad_codebook, s));
+  RenderBwdArgs a{};
+  fill_bin(a.bin, g, bbase, L, capacity, shift, 0);
+  int sort_cap = 1;
+  while (2 * sort_cap <= 32 * (m_atoms + 1)) sort_cap *= 2;
+  a.bin.sort_cap = sort_cap;
+  a.bin.cam = to_dev(*cam);
+  a.bin.tiles_x = (cam->width + 7) / 8;
+  a.bin.n_tiles = tiles_of(cam->width, cam->height, shift);
+  a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
+  a.dW = dW; a.grad_val = grad_topk_val;
+  Status* status = a.bin.status;
+  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  HIP_TRY(hipMemsetAsync(bbase + L.tile_count, 0, 4 * (size_t)L.max_tiles, s));
+  HIP_TRY(launch_render_bwd_view(a, s));
+  Status h{};
+  HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  if (h.any_overflow) {
+    g_required_pairs = (int64_t)h.max_pairs;
+    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(capacity) + " exceeded; need " +
+                                       std::to_string(h.max_pairs));
+  }
+  return SCOUP_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,288 @@
+// Codebook decode (Eq. 8): F = W_hat C, [P x M] x [M x D], on MFMA with float32
+// accumulation.  Input precisions: float32 (v_mfma_f32_32x32x2_f32),
+// bfloat16 (v_mfma_f32_32x32x16_bf16) and OCP FP8 E4M3 with power-of-two
+// per-tensor scales (v_mfma_scale_f32_32x32x64_f8f6f4, unit block scales).
+// Output float32 or bfloat16.
+//
+// Workgroup: 8 waves, a 128-pixel x D tile.  The 128 x M coefficient rows are
+// staged once in LDS; the codebook is pre-arranged in MFMA B-fragment order
+// (one 1 KB coalesced load per 32-column tile and k-step) and read from L2.
+// Wave w owns pixels [64 (w/4), +64) and columns [(w%4) D/4, +D/4).
+#include <hip/hip_runtime.h>
+
+#include "scoup_device.h"
+#include "scoup_internal.h"
+
+namespace scoup {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// k-step and fragment bytes per lane of each input type
+template <int T> struct Mfma;
+template <> struct Mfma<SCOUP_F32> { static constexpr int KS = 2, FB = 4, ES = 4; };
+template <> struct Mfma<SCOUP_BF16> { static constexpr int KS = 16, FB = 16, ES = 2; };
+template <> struct Mfma<SCOUP_FP8_E4M3> { static constexpr int KS = 64, FB = 32, ES = 1; };
+
+constexpr int kDecBM = 128;
+constexpr int kDecThreads = 512;
+
+// lane l of a 32x32 MFMA operand covers row/col (l % 32) and the k-slice
+// [(l / 32) * KS/2, +KS/2) of the k-step.
+// B operand (K x N = M x D here) from a float32 source, element (k, n) at
+// C[k * N + n] (or C[n * K + k] when transposed); columns beyond N are zero.
+template <int T>
+__global__ __launch_bounds__(256) void k_prep_codebook(const float* __restrict__ C, int M, int D, int kpad,
+                                                       int npad, int transposed, uint8_t* __restrict__ out,
+                                                       const float* scale_ptr) {
+  using F = Mfma<T>;
+  const long long total = (long long)(npad / 32) * (kpad / F::KS) * 64;   // (ct, ks, lane)
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int lane = (int)(t & 63);
+  const long long rest = t >> 6;
+  const int nks = kpad / F::KS;
+  const int ks = (int)(rest % nks), ct = (int)(rest / nks);
+  const int col = ct * 32 + (lane & 31);
+  const int k0 = ks * F::KS + (lane >> 5) * (F::KS / 2);
+  const float sc = scale_ptr ? *scale_ptr : 1.0f;
+  uint8_t* dst = out + t * F::FB;
+  for (int i = 0; i < F::KS / 2; ++i) {
+    const int k = k0 + i;
+    const float v = (k < M && col < D)
+                        ? (transposed ? C[(long long)col * M + k] : C[(long long)k * D + col]) * sc
+                        : 0.0f;
+    if (T == SCOUP_F32) reinterpret_cast<float*>(dst)[i] = v;
+    else if (T == SCOUP_BF16) reinterpret_cast<uint16_t*>(dst)[i] = f32_to_bf16_rne(v);
+    else dst[i] = f32_to_e4m3(v);
+  }
+}
+
+// power-of-two scale s with max|C| s <= 448 (FP8 E4M3 range), one workgroup
+__global__ __launch_bounds__(256) void k_fp8_scale(const float* __restrict__ C, long long n, float* scale) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (long long i = threadIdx.x; i < n; i += 256) m = fmaxf(m, fabsf(C[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float mx = red[0];
+    scale[0] = mx > 0.0f ? exp2f(floorf(log2f(448.0f / mx))) : 1.0f;
+  }
+}
+
+__device__ __forceinline__ void store_f(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_f(uint16_t* p, float v) { *p = f32_to_bf16_rne(v); }
+
+template <int T, int NCT, typename TOut>
+__global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restrict__ A, long long P, int M,
+                                                        int kpad, int kc, const uint8_t* __restrict__ Bp,
+                                                        int n_valid, int ldo, TOut* __restrict__ out,
+                                                        float out_mul, const float* __restrict__ cb_scale) {
+  using F = Mfma<T>;
+  extern __shared__ uint8_t sA[];                     // kDecBM rows of kc elements (+16 B pad)
+  const int row_bytes = kc * F::ES + 16;
+  const long long p0 = (long long)blockIdx.x * kDecBM;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int src_row = M * F::ES;
+  const int rh = wave >> 2, cq = wave & 3;
+  f16v acc[2][NCT];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[a][c] = (f16v){};
+  const int nks = kpad / F::KS;
+  const int ct0 = cq * NCT;
+  for (int k0 = 0; k0 < kpad; k0 += kc) {
+    const int kcur = min(kc, kpad - k0);
+    // stage rows [p0, p0+128) x k [k0, k0+kcur) in 16-byte chunks, zero beyond M and P
+    const int chunks = kcur * F::ES / 16;
+    for (int c = tid; c < kDecBM * chunks; c += kDecThreads) {
+      const int r = c / chunks, q = c - r * chunks;
+      i32x4 v = {0, 0, 0, 0};
+      const long long p = p0 + r;
+      const int off = k0 * F::ES + q * 16;
+      if (p < P) {
+        const uint8_t* src = A + p * src_row + off;
+        if (off + 16 <= src_row && (src_row & 15) == 0) {
+          v = *reinterpret_cast<const i32x4*>(src);
+        } else {
+          for (int b = 0; b < 16 && off + b < src_row; ++b) reinterpret_cast<uint8_t*>(&v)[b] = src[b];
+        }
+      }
+      *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kcur; kk += F::KS) {
+      const int ks = (k0 + kk) / F::KS;
+      const int kb = (kk + (lane >> 5) * (F::KS / 2)) * F::ES;   // byte offset in the LDS row
+      if constexpr (T == SCOUP_F32) {
+        const float a0 = *reinterpret_cast<const float*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
+        const float a1 = *reinterpret_cast<const float*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          const float b = reinterpret_cast<const float*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
+          acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b, acc[0][c], 0, 0, 0);
+          acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b, acc[1][c], 0, 0, 0);
+        }
+      } else if constexpr (T == SCOUP_BF16) {
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          const bf16x8 b = reinterpret_cast<const bf16x8*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
+          acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][c], 0, 0, 0);
+          acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][c], 0, 0, 0);
+        }
+      } else {
+        const i32x8 a0 = *reinterpret_cast<const i32x8*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
+        const i32x8 a1 = *reinterpret_cast<const i32x8*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          const i32x8 b = reinterpret_cast<const i32x8*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
+          // format 0 = FP8 E4M3 for both operands; E8M0 block scales 127 = 2^0
+          acc[0][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a0, b, acc[0][c], 0, 0, 0, 127, 0, 127);
+          acc[1][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a1, b, acc[1][c], 0, 0, 0, 127, 0, 127);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float mul = out_mul;
+  if (cb_scale) mul /= *cb_scale;
+  // D element (row 8(r/4) + 4(l/32) + r%4, col l%32) of each 32x32 tile
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long p = p0 + rh * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = (ct0 + c) * 32 + (lane & 31);
+        if (p < P && col < n_valid) store_f(out + p * ldo + col, acc[a][c][r] * mul);
+      }
+}
+
+int decode_npad(int d) {
+  if (d <= 128) return 128;
+  if (d <= 256) return 256;
+  if (d <= 512) return 512;
+  return 1024;
+}
+
+// K is padded (with zeros) to a multiple of both the MFMA k-step and one
+// 16-byte LDS chunk: 4 (float32), 16 (bfloat16), 64 (FP8).
+int decode_kalign(int in_dtype) { return in_dtype == SCOUP_F32 ? 4 : in_dtype == SCOUP_BF16 ? 16 : 64; }
+
+int decode_kpad(int m, int in_dtype) {
+  const int ka = decode_kalign(in_dtype);
+  return (m + ka - 1) / ka * ka;
+}
+
+size_t decode_codebook_bytes(int m, int d, int in_dtype) {
+  const int es = in_dtype == SCOUP_F32 ? 4 : in_dtype == SCOUP_BF16 ? 2 : 1;
+  return (size_t)decode_kpad(m, in_dtype) * decode_npad(d) * es;
+}
+
+// k-chunk staged in LDS per pass: at most 128 KB of coefficient rows
+int decode_kchunk(int m, int in_dtype) {
+  const int es = in_dtype == SCOUP_F32 ? 4 : in_dtype == SCOUP_BF16 ? 2 : 1;
+  const int kpad = decode_kpad(m, in_dtype);
+  const int cap = (128 * 1024 / kDecBM - 16) / es;         // elements per row
+  const int ka = decode_kalign(in_dtype);
+  const int kc = cap / ka * ka;
+  return kpad < kc ? kpad : kc;
+}
+
+size_t decode_lds_bytes(int m, int in_dtype) {
+  const int es = in_dtype == SCOUP_F32 ? 4 : in_dtype == SCOUP_BF16 ? 2 : 1;
+  return (size_t)kDecBM * (decode_kchunk(m, in_dtype) * es + 16);
+}
+
+template <int T, int NCT, typename TOut>
+static void launch_dec(const DecodeArgs& a, hipStream_t s, size_t lds, int grid) {
+  hipLaunchKernelGGL((k_decode<T, NCT, TOut>), dim3(grid), dim3(kDecThreads), lds, s,
+                     (const uint8_t*)a.coeff, a.P, a.m, a.kpad, decode_kchunk(a.m, a.in_dtype),
+                     (const uint8_t*)a.codebook_prep, a.d, a.ldo > 0 ? a.ldo : a.d, (TOut*)a.out, a.out_mul,
+                     a.cb_scale);
+}
+
+template <int T, typename TOut>
+static hipError_t dispatch_nct(const DecodeArgs& a, hipStream_t s, size_t lds, int grid) {
+  switch (decode_npad(a.d) / 128) {
+    case 1: launch_dec<T, 1, TOut>(a, s, lds, grid); break;
+    case 2: launch_dec<T, 2, TOut>(a, s, lds, grid); break;
+    case 4: launch_dec<T, 4, TOut>(a, s, lds, grid); break;
+    case 8: launch_dec<T, 8, TOut>(a, s, lds, grid); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int T, int NCT, typename TOut>
+static hipError_t set_lds(size_t bytes) {
+  return hipFuncSetAttribute((const void*)k_decode<T, NCT, TOut>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+hipError_t decode_set_lds_limits() {
+  const size_t b = 160 * 1024;
+  hipError_t e = hipSuccess;
+#define SETL(T, TO)                                                        \
+  if ((e = set_lds<T, 1, TO>(b)) != hipSuccess) return e;                 \
+  if ((e = set_lds<T, 2, TO>(b)) != hipSuccess) return e;                 \
+  if ((e = set_lds<T, 4, TO>(b)) != hipSuccess) return e;                 \
+  if ((e = set_lds<T, 8, TO>(b)) != hipSuccess) return e;
+  SETL(SCOUP_F32, float) SETL(SCOUP_F32, uint16_t) SETL(SCOUP_BF16, float) SETL(SCOUP_BF16, uint16_t)
+  SETL(SCOUP_FP8_E4M3, float) SETL(SCOUP_FP8_E4M3, uint16_t)
+#undef SETL
+  return e;
+}
+
+hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void* out, float* scale,
+                                hipStream_t s, int transposed) {
+  const int kpad = decode_kpad(m, in_dtype);
+  const int npad = decode_npad(d);
+  const int ks = in_dtype == SCOUP_F32 ? 2 : in_dtype == SCOUP_BF16 ? 16 : 64;
+  const long long total = (long long)(npad / 32) * (kpad / ks) * 64;
+  const int grid = (int)((total + 255) / 256);
+  if (in_dtype == SCOUP_FP8_E4M3) {
+    hipLaunchKernelGGL(k_fp8_scale, dim3(1), dim3(256), 0, s, C, (long long)m * d, scale);
+    hipLaunchKernelGGL(k_prep_codebook<SCOUP_FP8_E4M3>, dim3(grid), dim3(256), 0, s, C, m, d, kpad, npad,
+                       transposed, (uint8_t*)out, (const float*)scale);
+  } else if (in_dtype == SCOUP_BF16) {
+    hipLaunchKernelGGL(k_prep_codebook<SCOUP_BF16>, dim3(grid), dim3(256), 0, s, C, m, d, kpad, npad,
+                       transposed, (uint8_t*)out, (const float*)nullptr);
+  } else {
+    hipLaunchKernelGGL(k_prep_codebook<SCOUP_F32>, dim3(grid), dim3(256), 0, s, C, m, d, kpad, npad,
+                       transposed, (uint8_t*)out, (const float*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage) {
+  const size_t lds = decode_lds_bytes(a.m, a.in_dtype);
+  const int grid = (int)((a.P + kDecBM - 1) / kDecBM);
+  if (grid == 0) return hipSuccess;
+  StageTimer::begin(stage, s);
+  hipError_t e;
+  if (a.in_dtype == SCOUP_F32)
+    e = a.out_dtype == SCOUP_F32 ? dispatch_nct<SCOUP_F32, float>(a, s, lds, grid)
+                                 : dispatch_nct<SCOUP_F32, uint16_t>(a, s, lds, grid);
+  else if (a.in_dtype == SCOUP_BF16)
+    e = a.out_dtype == SCOUP_F32 ? dispatch_nct<SCOUP_BF16, float>(a, s, lds, grid)
+                                 : dispatch_nct<SCOUP_BF16, uint16_t>(a, s, lds, grid);
+  else
+    e = a.out_dtype == SCOUP_F32 ? dispatch_nct<SCOUP_FP8_E4M3, float>(a, s, lds, grid)
+                                 : dispatch_nct<SCOUP_FP8_E4M3, uint16_t>(a, s, lds, grid);
+  StageTimer::end(stage, s);
+  return e;
+}
+
+}  // namespace scoup

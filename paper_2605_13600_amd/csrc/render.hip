@@ -1,0 +1,159 @@
+// Sparse coefficient render (Eq. 7): W_hat_v(p) = sum_{i in N_{v,p}} w_hat_i e_i(v,p)
+// over K (atom, value) pairs per Gaussian, front-to-back weights e from Eq. 2.
+// gfx950, wave64: one 8x8 pixel block per workgroup (one wave); every pixel
+// keeps its dense M-wide coefficient row in LDS (stride M+1 to spread banks),
+// accumulates in float32 and writes the row once, converted to the output type.
+#include <hip/hip_runtime.h>
+
+#include "scoup_device.h"
+#include "scoup_internal.h"
+
+namespace scoup {
+
+constexpr int kRenderKMax = 16;
+
+__device__ __forceinline__ void store_out(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_out(uint16_t* p, float v) { *p = f32_to_bf16_rne(v); }
+__device__ __forceinline__ void store_out(uint8_t* p, float v) { *p = f32_to_e4m3(v); }
+
+template <typename OutT>
+__global__ __launch_bounds__(64) void k_render_coeff(
+    const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
+    unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
+    const int* __restrict__ topk_idx, const float* __restrict__ topk_val, int K, int M,
+    int sort_cap, OutT* __restrict__ out, float out_scale, float* __restrict__ t_final,
+    Status* st) {
+  extern __shared__ float rows[];          // 64 * (M+1) floats; aliased by the sort keys first
+  __shared__ GSplat s_g[64];
+  __shared__ int s_ti[64 * kRenderKMax];
+  __shared__ float s_tv[64 * kRenderKMax];
+  if (st->view_overflow) return;
+  const int tile = blockIdx.x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const unsigned int start = tile_start[tile];
+  const int L = (int)(tile_start[tile + 1] - start);
+  const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int px = tx * 8 + lx, py = ty * 8 + ly;
+  const bool inside = px < W && py < H;
+  const int stride = M + 1;
+
+  if (L > 0 && L <= sort_cap) {            // depth order of the block's list, in LDS
+    unsigned long long* sk = reinterpret_cast<unsigned long long*>(rows);
+    int n2 = 1;
+    while (n2 < L) n2 <<= 1;
+    for (int j = lane; j < n2; j += 64) sk[j] = j < L ? keys[start + j] : ~0ull;
+    __syncthreads();
+    bitonic_lds(sk, n2, lane, 64);
+    for (int j = lane; j < L; j += 64) keys[start + j] = sk[j];
+    __syncthreads();
+  }
+  for (int j = lane; j < 64 * stride; j += 64) rows[j] = 0.0f;
+  __syncthreads();
+
+  float* myrow = rows + lane * stride;
+  float T = 1.0f;
+  bool done = !inside;
+  unsigned long long count = 0;
+  const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
+  const int tile_x0 = tx * 8, tile_y0 = ty * 8;
+  for (int b0 = 0; b0 < L; b0 += 64) {
+    if (__ballot(!done) == 0ull) break;
+    const int j = b0 + lane;
+    if (j < L) {
+      const unsigned int id = (unsigned int)keys[start + j];
+      s_g[lane] = splats[id];
+      for (int k = 0; k < K; ++k) {
+        s_ti[lane * K + k] = topk_idx[(long long)id * K + k];
+        s_tv[lane * K + k] = topk_val[(long long)id * K + k];
+      }
+    }
+    __syncthreads();
+    const int nb = min(64, L - b0);
+    for (int k = 0; k < nb; ++k) {
+      const GSplat g = s_g[k];
+      const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
+      const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
+      const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
+      const float q = fmaf(u, u, v * v);
+      const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
+      const bool take = !done && alpha >= kAlphaMin;
+      if (__ballot(take) == 0ull) continue;
+      float e = 0.0f;
+      if (take) {
+        const float testT = T * (1.0f - alpha);
+        if (testT < kTMin) {
+          done = true;
+        } else {
+          e = alpha * T;
+          T = testT;
+        }
+      }
+      if (e > 0.0f) {
+        ++count;
+        for (int kk = 0; kk < K; ++kk) {
+          const int jj = s_ti[k * K + kk];
+          if (jj >= 0 && jj < M) myrow[jj] += e * s_tv[k * K + kk];
+          else if (jj >= M) atomicOr(&st->data_error, 4u);
+        }
+      }
+      if (__ballot(!done) == 0ull) break;
+    }
+    __syncthreads();
+  }
+  if (inside && t_final) t_final[(long long)py * W + px] = T;
+  // contributions: one atomic per wave
+  for (int o = 32; o >= 1; o >>= 1) count += __shfl_xor(count, o, 64);
+  if (lane == 0 && count) atomicAdd(&st->contrib, count);
+  // write the 8x8 block's rows, atoms fastest (coalesced per pixel row)
+  for (int p = 0; p < 64; ++p) {
+    const int ox = tile_x0 + (p & 7), oy = tile_y0 + (p >> 3);
+    if (ox >= W || oy >= H) continue;
+    OutT* dst = out + ((long long)oy * W + ox) * M;
+    const float* src = rows + p * stride;
+    for (int jj = lane; jj < M; jj += 64) store_out(dst + jj, src[jj] * out_scale);
+  }
+}
+
+hipError_t launch_render_view(const RenderViewArgs& a, hipStream_t s) {
+  hipError_t e = launch_bin_view(a.bin, s);
+  if (e != hipSuccess) return e;
+  const BinArgs& b = a.bin;
+  const size_t lds = sizeof(float) * 64 * (size_t)(a.m_atoms + 1);
+  StageTimer::begin(kStRender, s);
+  switch (a.out_dtype) {
+    case SCOUP_F32:
+      hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start,
+                         b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
+                         a.m_atoms, b.sort_cap, (float*)a.out, a.out_scale, a.t_final, b.status);
+      break;
+    case SCOUP_BF16:
+      hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
+                         b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint16_t*)a.out, a.out_scale,
+                         a.t_final, b.status);
+      break;
+    default:
+      hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
+                         b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint8_t*)a.out, a.out_scale,
+                         a.t_final, b.status);
+      break;
+  }
+  StageTimer::end(kStRender, s);
+  return hipGetLastError();
+}
+
+hipError_t render_set_lds_limits() {
+  const int bytes = 160 * 1024 - (int)(sizeof(GSplat) * 64 + 8 * 64 * kRenderKMax) - 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)k_render_coeff<float>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_render_coeff<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_render_coeff<uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes);
+}
+
+}  // namespace scoup

@@ -67,8 +67,68 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
+// float32 -> bfloat16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((unsigned int)b << 16); }
+
+// float32 -> OCP FP8 E4M3 (bias 7, 3 mantissa bits, max 448, no infinities),
+// round to nearest even, saturating to +-448.
+__device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
+  const unsigned int u = __float_as_uint(x);
+  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  const float a = fabsf(x);
+  if (a != a) return (uint8_t)(sign | 0x7f);
+  if (a >= 464.0f) return (uint8_t)(sign | 0x7e);
+  if (a < 0.015625f) {                       // subnormal range: multiples of 2^-9
+    const int q = (int)rintf(a * 512.0f);    // 0..8, 8 becomes the smallest normal
+    return (uint8_t)(sign | q);
+  }
+  int e;
+  const float f = frexpf(a, &e);             // a = f 2^e, f in [0.5, 1)
+  int ex = e - 1;
+  int mq = (int)rintf((f * 2.0f - 1.0f) * 8.0f);
+  if (mq == 8) { mq = 0; ++ex; }
+  const int biased = ex + 7;
+  if (biased > 15 || (biased == 15 && mq == 7)) return (uint8_t)(sign | 0x7e);
+  return (uint8_t)(sign | (biased << 3) | mq);
+}
+
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// bitonic sorting network, every comparator ascending (min to the lower
+// index): positions past the end act as +infinity and are never touched.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cmp_swap(unsigned long long* a, unsigned long long* b) {
+  const unsigned long long x = *a, y = *b;
+  if (x > y) { *a = y; *b = x; }
+}
+
+__device__ inline void bitonic_lds(unsigned long long* s, int n2, int tid, int nthreads) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    const int hk = k >> 1;
+    for (int i = tid; i < (n2 >> 1); i += nthreads) {
+      const int blk = i / hk, off = i - blk * hk;
+      cmp_swap(&s[blk * k + off], &s[blk * k + k - 1 - off]);
+    }
+    __syncthreads();
+    for (int j = k >> 2; j >= 1; j >>= 1) {
+      for (int i = tid; i < (n2 >> 1); i += nthreads) {
+        const int blk = i / j, off = i - blk * j;
+        const int a = blk * 2 * j + off;
+        cmp_swap(&s[a], &s[a + j]);
+      }
+      __syncthreads();
+    }
+  }
 }
 
 }  // namespace scoup

@@ -18,20 +18,28 @@ struct StageTimer {
   static void collect();   // after the stream is synchronised
 };
 
-struct UpliftViewArgs {
+// Projection + tile binning + per-tile depth order of one view.
+struct BinArgs {
   const float* means;
   const float* log_scales;
   const float* quats;
   const float* opacities;
   long long n;
   CamDev cam;
+  int tile_shift;          // tile edge = 1 << tile_shift pixels
   int tiles_x, n_tiles;
+  int sort_cap;            // tiles with longer lists are sorted in global memory
   GSplat* splats;
   unsigned int* tile_count;
   unsigned int* tile_cursor;
   unsigned int* tile_start;
   unsigned long long* keys;
   long long capacity;
+  Status* status;
+};
+
+struct UpliftViewArgs {
+  BinArgs bin;
   const int* rmap;
   int n_regions;
   long long region_base;
@@ -39,9 +47,55 @@ struct UpliftViewArgs {
   const float* code_val;
   int k_code, m_atoms;
   float* acc;
-  Status* status;
 };
 
+hipError_t launch_bin_view(const BinArgs& a, hipStream_t s);
+
+struct RenderViewArgs {
+  BinArgs bin;
+  const int* topk_idx;
+  const float* topk_val;
+  int k, m_atoms;
+  int out_dtype;           // scoup_dtype of the coefficient map
+  void* out;
+  float out_scale;
+  float* t_final;
+};
+hipError_t launch_render_view(const RenderViewArgs& a, hipStream_t s);
+hipError_t render_set_lds_limits();
+
+struct DecodeArgs {
+  const void* coeff;       // [P x m] in in_dtype
+  long long P;
+  int m, d, kpad;
+  int in_dtype, out_dtype;
+  const void* codebook_prep;   // codebook in MFMA B-fragment order (launch_prep_codebook)
+  const float* cb_scale;       // device scale applied to the FP8 codebook (NULL otherwise)
+  float out_mul;               // 1 / coefficient scale
+  void* out;                   // [P x ldo] in out_dtype, columns < d written
+  int ldo;                     // output row stride (0 = d)
+};
+int decode_kpad(int m, int in_dtype);
+int decode_npad(int d);
+size_t decode_codebook_bytes(int m, int d, int in_dtype);
+hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void* out, float* scale,
+                                hipStream_t s, int transposed = 0);
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage = kStDecode);
+
+struct RenderBwdArgs {
+  BinArgs bin;
+  const int* topk_idx;
+  const float* topk_val;
+  int k, m_atoms;
+  const float* dW;             // [P x m] float32 gradient of the coefficient map
+  float* grad_val;             // [N x k] float32, accumulated
+};
+hipError_t launch_render_bwd_view(const RenderBwdArgs& a, hipStream_t s);
+hipError_t render_bwd_set_lds_limits();
+// grad_C[m x d] += coeff^T [m x P] * G [P x d], float32 MFMA, split over pixels
+hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int m, int d, float* grad_C,
+                            hipStream_t s);
+hipError_t decode_set_lds_limits();
 hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s);
 hipError_t launch_topk(const float* acc, long long n, int m, int k, int* idx, float* val, hipStream_t s);
 hipError_t launch_add_contrib(unsigned long long* dst, const Status* st, hipStream_t s);

@@ -24,7 +24,8 @@ namespace scoup {
 __global__ __launch_bounds__(256) void k_project(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ opacities, long long n,
-    CamDev cam, int tiles_x, GSplat* __restrict__ out, unsigned int* __restrict__ tile_count) {
+    CamDev cam, int tiles_x, int tile_shift, GSplat* __restrict__ out,
+    unsigned int* __restrict__ tile_count) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   GSplat s;
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(256) void k_project(
   s.bx0 = (int16_t)x0; s.bx1 = (int16_t)x1; s.by0 = (int16_t)y0; s.by1 = (int16_t)y1;
   s.depth_bits = __float_as_uint((float)z);
   out[i] = s;
-  const int tx0 = s.bx0 / kTile, tx1 = s.bx1 / kTile, ty0 = s.by0 / kTile, ty1 = s.by1 / kTile;
+  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
+  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_count[ty * tiles_x + tx], 1u);
 }
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(1024) void k_tile_scan(unsigned int* __restrict__ t
 // emit one (depth, id) key per (Gaussian, tile) into the tile's bucket
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n,
-                                              int tiles_x, const unsigned int* __restrict__ tile_start,
+                                              int tiles_x, int tile_shift,
+                                              const unsigned int* __restrict__ tile_start,
                                               unsigned int* __restrict__ tile_cursor,
                                               unsigned long long* __restrict__ keys, const Status* st) {
   if (st->view_overflow) return;
@@ -175,7 +178,8 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
   const GSplat s = splats[i];
   if (s.bx0 > s.bx1) return;
   const unsigned long long key = ((unsigned long long)s.depth_bits << 32) | (unsigned long long)i;
-  const int tx0 = s.bx0 / kTile, tx1 = s.bx1 / kTile, ty0 = s.by0 / kTile, ty1 = s.by1 / kTile;
+  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
+  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
       const int t = ty * tiles_x + tx;
@@ -184,44 +188,16 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
     }
 }
 
-// ---------------------------------------------------------------------------
-// bitonic sorting network, every comparator ascending (min to the lower
-// index): positions past the end act as +infinity and are never touched.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void cmp_swap(unsigned long long* a, unsigned long long* b) {
-  const unsigned long long x = *a, y = *b;
-  if (x > y) { *a = y; *b = x; }
-}
-
-__device__ void bitonic_lds(unsigned long long* s, int n2, int tid, int nthreads) {
-  for (int k = 2; k <= n2; k <<= 1) {
-    const int hk = k >> 1;
-    for (int i = tid; i < (n2 >> 1); i += nthreads) {
-      const int blk = i / hk, off = i - blk * hk;
-      cmp_swap(&s[blk * k + off], &s[blk * k + k - 1 - off]);
-    }
-    __syncthreads();
-    for (int j = k >> 2; j >= 1; j >>= 1) {
-      for (int i = tid; i < (n2 >> 1); i += nthreads) {
-        const int blk = i / j, off = i - blk * j;
-        const int a = blk * 2 * j + off;
-        cmp_swap(&s[a], &s[a + j]);
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // Tiles whose list exceeds the LDS capacity are sorted in place in global
 // memory by one workgroup (rare; correctness path for dense tiles).
 __global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restrict__ keys,
                                                    const unsigned int* __restrict__ tile_start,
-                                                   const Status* st) {
+                                                   int sort_cap, const Status* st) {
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const unsigned int start = tile_start[tile];
   const long long L = (long long)tile_start[tile + 1] - start;
-  if (L <= kSortCap) return;
+  if (L <= sort_cap) return;
   unsigned long long* s = keys + start;
   long long n2 = 1;
   while (n2 < L) n2 <<= 1;
@@ -396,12 +372,12 @@ __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += s
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s) {
+hipError_t launch_bin_view(const BinArgs& a, hipStream_t s) {
   const int nb = (int)((a.n + 255) / 256);
   if (a.n > 0) {
     StageTimer::begin(kStProject, s);
     hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, s, a.means, a.log_scales, a.quats,
-                       a.opacities, a.n, a.cam, a.tiles_x, a.splats, a.tile_count);
+                       a.opacities, a.n, a.cam, a.tiles_x, a.tile_shift, a.splats, a.tile_count);
     StageTimer::end(kStProject, s);
   }
   StageTimer::begin(kStScan, s);
@@ -410,17 +386,25 @@ hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s) {
   StageTimer::end(kStScan, s);
   if (a.n > 0) {
     StageTimer::begin(kStEmit, s);
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_start,
-                       a.tile_cursor, a.keys, a.status);
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_shift,
+                       a.tile_start, a.tile_cursor, a.keys, a.status);
     StageTimer::end(kStEmit, s);
   }
   StageTimer::begin(kStSortBig, s);
-  hipLaunchKernelGGL(k_sort_big, dim3(a.n_tiles), dim3(1024), 0, s, a.keys, a.tile_start, a.status);
+  hipLaunchKernelGGL(k_sort_big, dim3(a.n_tiles), dim3(1024), 0, s, a.keys, a.tile_start, a.sort_cap,
+                     a.status);
   StageTimer::end(kStSortBig, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s) {
+  hipError_t e = launch_bin_view(a.bin, s);
+  if (e != hipSuccess) return e;
+  const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_acc, dim3(a.n_tiles), dim3(kTileThreads), 0, s, a.splats,
-                     a.tile_start, a.keys, a.tiles_x, a.cam.width, a.cam.height, a.rmap, a.n_regions,
-                     a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, a.status);
+  hipLaunchKernelGGL(k_composite_acc, dim3(b.n_tiles), dim3(kTileThreads), 0, s, b.splats,
+                     b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.rmap, a.n_regions,
+                     a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, b.status);
   StageTimer::end(kStComposite, s);
   return hipGetLastError();
 }

@@ -1,0 +1,136 @@
+"""GPU parity of the sparse coefficient render (Eq. 7) and the codebook decode (Eq. 8).
+
+Tolerances:
+* FP32 coefficient map, per pixel: ||dW||_1 <= 1e-5 ||W_ref||_1 + amb(p) + 1e-9,
+  amb(p) the oracle's ambiguity mass of the pixel (|weight change| of its
+  marginal decisions; every w_hat sums to one, so it bounds the L1 change);
+* BF16 / FP8 maps: elementwise within the format's rounding (2^-8 / 2^-3 relative,
+  plus the smallest subnormal for FP8) of the FP32 result;
+* decode on seeded float32 inputs: FP32 within 1e-5 relative of the FP64 product
+  (row norm), BF16 and FP8 cosine error 1 - cos <= 2e-2 per pixel;
+* render + decode end to end: cosine error against the FP64 oracle <= 2e-2 (BF16),
+  1e-5 (FP32); statistics printed for FP8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_13600_amd as P
+import scenegen as sg
+from oracle import composite as OC
+from oracle import render as OR
+from tests import _scenes as S
+from tests._gpu import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _amb_per_pixel(rr, width, height):
+    amb = np.zeros(width * height)
+    for pix, gi, delta, _ in OC.ambiguity(rr.weights.marginal):
+        amb[pix] += delta.sum()
+    return amb
+
+
+def _render_scene(n=20_000, res=(200, 150), m=64, k=4, seed=3):
+    g = sg.make_gaussians(seed, n, (5.0, 5.0, 2.0), -3.6, 0.5, False, "beta")
+    cams = sg.orbit_cameras(seed + 1, 2, 12.0, 1.0, 4.0, 1.0, 0.5, res[0], res[1], 60.0)
+    ti, tv = sg.random_topk(seed + 2, n, m, k)
+    return g, cams, ti, tv
+
+
+@pytest.mark.parametrize("res,m,k", [((200, 150), 64, 4), ((203, 77), 256, 8), ((64, 48), 512, 16)])
+def test_render_fp32_matches_oracle(res, m, k):
+    require_gpu()
+    g, cams, ti, tv = _render_scene(res=res, m=m, k=k)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    for cam in cams:
+        W, tf, nc, _ = P.render_coeff(dg, dti, dtv, cam, m, dtype="f32")
+        torch.cuda.synchronize()
+        rr = OR.render_coeff(g, ti, tv, cam, m, track_marginal=True)
+        amb = _amb_per_pixel(rr, cam.width, cam.height)
+        got = W.cpu().numpy().reshape(-1, m).astype(np.float64)
+        err = np.abs(got - rr.coeff).sum(1)
+        ref = np.abs(rr.coeff).sum(1)
+        assert (err <= 1e-5 * ref + amb + 1e-9).all(), float((err - 1e-5 * ref - amb).max())
+        assert np.allclose(tf.cpu().numpy().reshape(-1), rr.t_final, rtol=2e-5, atol=1e-7)
+        slack = sum(s for *_, s in OC.ambiguity(rr.weights.marginal))
+        assert abs(nc - rr.weights.n_contrib) <= slack
+        print(f"[render {res} M={m}] contrib={nc} max L1 rel err={float((err / np.maximum(ref, 1e-30)).max()):.3g}")
+
+
+def test_render_low_precision_outputs():
+    require_gpu()
+    g, cams, ti, tv = _render_scene(res=(160, 120), m=256, k=8)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    f32, _, _, _ = P.render_coeff(dg, dti, dtv, cams[0], 256, dtype="f32")
+    b16, _, _, _ = P.render_coeff(dg, dti, dtv, cams[0], 256, dtype="bf16")
+    f8, _, _, sc = P.render_coeff(dg, dti, dtv, cams[0], 256, dtype="fp8")
+    a = f32.cpu().numpy().astype(np.float64)
+    b = b16.float().cpu().numpy().astype(np.float64)
+    assert (np.abs(b - a) <= 2.0 ** -8 * np.abs(a) + 1e-30).all()
+    c = f8.view(torch.float8_e4m3fn).float().cpu().numpy().astype(np.float64) / sc
+    assert (np.abs(c - a) <= 2.0 ** -3 * np.abs(a) + 2.0 ** -9 / sc).all()
+
+
+def _cos_err(F, R, mask=None):
+    F = np.asarray(F, np.float64); R = np.asarray(R, np.float64)
+    nf, nr = np.linalg.norm(F, axis=1), np.linalg.norm(R, axis=1)
+    ok = (nr > 0) if mask is None else mask
+    return 1.0 - (F[ok] * R[ok]).sum(1) / (nf[ok] * nr[ok])
+
+
+@pytest.mark.parametrize("m,d", [(64, 512), (100, 512), (256, 512), (512, 512), (256, 128), (256, 1024)])
+def test_decode_against_fp64(m, d):
+    require_gpu()
+    rng = np.random.default_rng(m + d)
+    Pn = 1000 + 77
+    A = rng.random((Pn, m)).astype(np.float32)
+    A *= (rng.random((Pn, m)) < 0.1)                     # sparse-ish rows like rendered maps
+    A[:5] = 0
+    C = sg.random_codebook(m, m, d)
+    ref = A.astype(np.float64) @ C.astype(np.float64)
+    Ct = torch.from_numpy(C).cuda()
+    At = torch.from_numpy(A).cuda()
+    F32 = P.decode(At, Ct, "f32", out_dtype="f32").cpu().numpy()
+    rn = np.linalg.norm(ref, axis=1, keepdims=True)
+    assert (np.abs(F32 - ref) <= 1e-5 * rn + 1e-12).all()
+    F16 = P.decode(At.to(torch.bfloat16), Ct, "bf16", out_dtype="bf16").float().cpu().numpy()
+    e16 = _cos_err(F16, ref)
+    q8 = torch.from_numpy(A * 256.0).cuda().to(torch.float8_e4m3fn).view(torch.uint8)
+    F8 = P.decode(q8, Ct, "fp8", coeff_scale=256.0, out_dtype="f32").cpu().numpy()
+    e8 = _cos_err(F8, ref)
+    print(f"[decode M={m} D={d}] cos err bf16 max {e16.max():.2e} fp8 max {e8.max():.2e} mean {e8.mean():.2e}")
+    assert e16.max() <= 2e-2 and e8.max() <= 2e-2
+    assert np.abs(F16[:5]).max() == 0 and np.abs(F8[:5]).max() == 0
+
+
+def test_render_decode_end_to_end_scene_rows():
+    """The 1M-Gaussian scene's Gaussians with synthetic Top-8 over M=256, codebook
+    256x512, one 1440x1080 view; 3000 sampled pixels against the FP64 oracle."""
+    require_gpu()
+    sc = sg.make_scene("scene", n_views=1)
+    g = sc.gaussians
+    cam = sg.orbit_cameras(77, 100, 12.0, 1.0, 4.0, 1.0, 0.5, 1440, 1080, 60.0)[0]
+    ti, tv = sg.random_topk(11, g.n, 256, 8)
+    C = sg.random_codebook(12, 256, 512)
+    dg = P.gaussians_to_device(g)
+    dti, dtv, Ct = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda(), torch.from_numpy(C).cuda()
+    pix = np.random.default_rng(0).choice(1440 * 1080, 3000, replace=False)
+    mask = np.zeros(1440 * 1080, bool); mask[pix] = True
+    rr = OR.render_coeff(g, ti, tv, cam, 256, pixel_mask=mask)
+    Fref = OR.decode(rr.coeff, C)
+    cov = rr.t_final < 1.0
+    stats = {}
+    for dt in ("f32", "bf16", "fp8"):
+        W, tf, nc, scl = P.render_coeff(dg, dti, dtv, cam, 256, dtype=dt)
+        F = P.decode(W, Ct, dt, coeff_scale=scl, out_dtype="f32" if dt == "f32" else "bf16")
+        Fs = F.reshape(-1, 512)[torch.from_numpy(rr.pixels).cuda()].float().cpu().numpy()
+        e = _cos_err(Fs, Fref, cov)
+        stats[dt] = (float(e.max()), float(np.percentile(e, 99)), float(e.mean()))
+    print(f"[render+decode 1440x1080] contrib={nc} covered={int(cov.sum())} cos err (max,p99,mean) {stats}")
+    assert stats["f32"][0] <= 1e-5
+    assert stats["bf16"][0] <= 2e-2
+    assert stats["fp8"][0] <= 2e-2
