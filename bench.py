@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 not used
-STAGES = ["project", "tile_scan", "emit", "dense_tile_sort", "composite_accumulate", "topk",
-          "render", "decode", "render_backward", "backward_gemm"]
+STAGES = ["project", "pair_scan", "emit", "tile_sort", "composite", "topk",
+          "render", "decode", "render_backward", "backward_gemm", "row_build"]
 
 
 def log(msg):
@@ -164,8 +164,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        a, nc = P.uplift_accumulate(dg, dv, acc=acc, workspace=ws)
-        idx, val = P.topk(a, k)
+        idx, val, a, nc = P.uplift(dg, dv, k, workspace=ws, acc=acc)
         return nc
 
     for i in range(args.warmup):
@@ -195,10 +194,10 @@ def main():
 
     # roofline of the dominant kernel (compositing + accumulation, one launch per view)
     dom = max(stages, key=lambda s: stages[s]["total_ms"])
-    comp = stages["composite_accumulate"]
+    comp = stages["composite"]
     per_launch_flops = nc / sc.views.n_views * flops_per_contribution(sc.views.k_code)
     achieved = per_launch_flops / (comp["avg_us"] * 1e-6) / 1e12
-    roofline = dict(kernel="composite_accumulate", dominant_stage=dom, bound="alu",
+    roofline = dict(kernel="composite", dominant_stage=dom, bound="alu",
                     achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 5), traffic=None,
                     per_launch=f"{nc / sc.views.n_views:.4g} contributions x "

@@ -95,11 +95,16 @@ typedef struct {
   int32_t m_atoms;
 } scoup_views;
 
-/* Workspace bytes for scoup_uplift / scoup_uplift_accumulate given a capacity
- * for (Gaussian, 16x16-tile) pairs of one view.  A capacity of 0 picks a
- * default of 8 pairs per Gaussian.                                           */
+/* Workspace bytes for scoup_uplift / scoup_uplift_accumulate.
+ *   pair_capacity  capacity for (Gaussian, 16x16-tile) pairs of one view
+ *                  (0 picks 4 pairs per Gaussian)
+ *   view_batch     views whose per-pair records are kept before they are summed
+ *                  into the accumulator (0 = all views: one pass over acc)
+ * The workspace holds, per view of a batch, (n+1) pair offsets and two 8-byte
+ * region records per pair, plus one view's projected splats and sort buffers
+ * (about n*52 + pair_capacity*(24.25 + 16*view_batch) + 4*(n+1)*view_batch bytes). */
 size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* views,
-                                    int64_t pair_capacity);
+                                    int64_t pair_capacity, int32_t view_batch);
 
 /* After SCOUP_E_WORKSPACE: the pair capacity the failed call needed (the
  * largest per-view pair count it saw).  Thread-local.                       */
@@ -115,17 +120,20 @@ int64_t scoup_required_pair_capacity(void);
  * Gaussian that would take T below 1e-4 is excluded and ends the pixel),
  * G2D the EWA splat with +0.3 px^2 dilation and the 1.3 tan(fov/2) Jacobian
  * clamp, depth order by float32(view depth) with ties to the lower index.
- *   acc        device float32 [n*m], row-major (Gaussian-major)
- *   accumulate 0: acc is overwritten (zeroed first); 1: results are added to
- *              the values already in acc (resume over a further view set)
- *   n_contrib  device uint64 [1] or NULL; receives (+=) the number of
- *              Gaussian-pixel contributions (terms e > 0) composited
- * Returns SCOUP_E_WORKSPACE if a view's pair count exceeds the capacity the
- * workspace was sized for (acc is then incomplete; call again with a larger
- * workspace), SCOUP_E_DATA if a region id is >= the view's region count.    */
+ *   acc           device float32 [n*m], row-major (Gaussian-major)
+ *   accumulate    0: acc is overwritten (zeroed first); 1: results are added to
+ *                 the values already in acc (resume over a further view set)
+ *   pair_capacity, view_batch  as given to scoup_uplift_workspace_bytes
+ *   ws, ws_bytes  at least scoup_uplift_workspace_bytes(n, views, pair_capacity, view_batch)
+ *   n_contrib     device uint64 [1] or NULL; receives (+=) the number of
+ *                 Gaussian-pixel contributions (terms e > 0) composited
+ * Returns SCOUP_E_WORKSPACE if the workspace is too small or a view's pair
+ * count exceeds pair_capacity (acc is then incomplete; call again with
+ * scoup_required_pair_capacity()), SCOUP_E_DATA if a region id is >= the
+ * view's region count or a code atom index is >= m.                         */
 scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views* views,
-                                     float* acc, int32_t accumulate,
-                                     void* ws, size_t ws_bytes,
+                                     float* acc, int32_t accumulate, int64_t pair_capacity,
+                                     int32_t view_batch, void* ws, size_t ws_bytes,
                                      unsigned long long* n_contrib, void* stream);
 
 /* Top-K filter and L1 normalisation of Eq. 6, per row of acc (n rows of m):
@@ -140,12 +148,13 @@ scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k,
                         int32_t* idx, float* val, void* stream);
 
 /* The full uplift of Algorithm 1: acc is zeroed, accumulated over every view
- * (scoup_uplift_accumulate) and reduced to k coefficients per Gaussian
- * (scoup_topk).  Arguments as above.                                        */
+ * and reduced to k coefficients per Gaussian (Eq. 6, as scoup_topk; fused
+ * into the last accumulation pass).  Requires 1 <= k <= min(64, m) and
+ * m <= 4096.  Other arguments as scoup_uplift_accumulate.                   */
 scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* views, int32_t k,
-                          float* acc, int32_t* topk_idx, float* topk_val,
-                          void* ws, size_t ws_bytes, unsigned long long* n_contrib,
-                          void* stream);
+                          float* acc, int32_t* topk_idx, float* topk_val, int64_t pair_capacity,
+                          int32_t view_batch, void* ws, size_t ws_bytes,
+                          unsigned long long* n_contrib, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Sparse coefficient render (Eq. 7), decode (Eq. 8) and their backward
@@ -218,8 +227,9 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
  * id `stage`, the summed kernel time in milliseconds and the launch count
  * accumulated by completed calls since the last reset; it returns 0 on
  * success and -1 for an unknown stage.  Stage ids:
- *   0 project  1 tile scan  2 emit  3 dense-tile sort  4 composite+accumulate
+ *   0 project  1 pair scan  2 emit  3 tile sort  4 composite
  *   5 top-k    6 render     7 decode  8 render backward  9 backward GEMMs
+ *   10 accumulator row build
  * Process-wide state; not meant for concurrent calls from several threads. */
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);

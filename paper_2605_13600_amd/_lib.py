@@ -31,14 +31,16 @@ class Views(C.Structure):
 
 # every exported symbol of include/scoup.h with its signature
 SIGNATURES = {
-    "scoup_uplift_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Views), C.c_int64]),
+    "scoup_uplift_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Views), C.c_int64, C.c_int32]),
     "scoup_required_pair_capacity": (C.c_int64, []),
     "scoup_uplift_accumulate": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_void_p, C.c_int32,
-                                          C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+                                          C.c_int64, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                          C.c_void_p]),
     "scoup_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
     "scoup_uplift": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_int32, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+                               C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                               C.c_void_p]),
     "scoup_render_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Camera), C.c_int64]),
     "scoup_render_coeff": (C.c_int, [C.POINTER(Gaussians), C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                      C.POINTER(Camera), C.c_void_p, C.c_int, C.c_float, C.c_void_p,

@@ -140,33 +140,50 @@ def _workspace(device) -> Workspace:
     return _default_ws[key]
 
 
-def uplift_accumulate(g: DeviceGaussians, views: DeviceViews, acc: Optional[torch.Tensor] = None,
-                      accumulate: bool = False, stream=None, workspace: Optional[Workspace] = None,
-                      pair_capacity: int = 0):
-    """acc (N, M) float32 += Eq. 5 over every view (zeroed first unless ``accumulate``).
-    Returns (acc, n_contrib)."""
+WORKSPACE_LIMIT = 48 << 30   # the uplift workspace is capped here by batching views
+
+
+def _uplift_call(g: DeviceGaussians, views: DeviceViews, acc: torch.Tensor, accumulate: bool, k: int,
+                 idx: Optional[torch.Tensor], val: Optional[torch.Tensor], stream, workspace,
+                 pair_capacity: int, view_batch: int):
     lib = L.load()
     dev = g.means.device
-    if acc is None:
-        acc = torch.empty((g.n, views.m_atoms), dtype=torch.float32, device=dev)
     ws = workspace or _workspace(dev)
     gs, vs = g.struct(), views.struct()
-    key = (g.n, views.n_views, tuple(views._moff.tolist()[-1:]))
-    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    key = ("uplift", g.n, views.n_views, int(views._moff[-1]))
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0), 4 * g.n, 1 << 16)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     for _ in range(4):
-        nbytes = lib.scoup_uplift_workspace_bytes(g.n, C.byref(vs), cap)
+        vb = int(view_batch) if view_batch else max(1, views.n_views)
+        while vb > 1 and lib.scoup_uplift_workspace_bytes(g.n, C.byref(vs), cap, vb) > WORKSPACE_LIMIT:
+            vb = (vb + 1) // 2
+        nbytes = lib.scoup_uplift_workspace_bytes(g.n, C.byref(vs), cap, vb)
         buf = ws.get(nbytes)
         cnt.zero_()
-        st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), _ptr(acc), int(accumulate),
-                                         _ptr(buf), buf.numel(), _ptr(cnt), _stream(stream))
+        if k > 0:
+            st = lib.scoup_uplift(C.byref(gs), C.byref(vs), k, _ptr(acc), _ptr(idx), _ptr(val), cap, vb,
+                                  _ptr(buf), buf.numel(), _ptr(cnt), _stream(stream))
+        else:
+            st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), _ptr(acc), int(accumulate), cap, vb,
+                                             _ptr(buf), buf.numel(), _ptr(cnt), _stream(stream))
         if st == L.E_WORKSPACE:
-            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            cap = int(lib.scoup_required_pair_capacity() * 1.1) + 4096
             _capacity_cache[key] = cap
             continue
         _check(st)
-        return acc, int(cnt.item())
+        return int(cnt.item())
     raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+def uplift_accumulate(g: DeviceGaussians, views: DeviceViews, acc: Optional[torch.Tensor] = None,
+                      accumulate: bool = False, stream=None, workspace: Optional[Workspace] = None,
+                      pair_capacity: int = 0, view_batch: int = 0):
+    """acc (N, M) float32 += Eq. 5 over every view (zeroed first unless ``accumulate``).
+    Returns (acc, n_contrib)."""
+    if acc is None:
+        acc = torch.empty((g.n, views.m_atoms), dtype=torch.float32, device=g.means.device)
+    nc = _uplift_call(g, views, acc, accumulate, 0, None, None, stream, workspace, pair_capacity, view_batch)
+    return acc, nc
 
 
 def topk(acc: torch.Tensor, k: int, stream=None):
@@ -180,12 +197,16 @@ def topk(acc: torch.Tensor, k: int, stream=None):
 
 
 def uplift(g: DeviceGaussians, views: DeviceViews, k: int, stream=None, workspace=None,
-           pair_capacity: int = 0):
-    """Algorithm 1: accumulate over all views, then Top-K.  Returns
-    (idx (N,k) int32, val (N,k) float32, acc (N,M) float32, n_contrib)."""
-    acc, nc = uplift_accumulate(g, views, stream=stream, workspace=workspace,
-                                pair_capacity=pair_capacity)
-    idx, val = topk(acc, k, stream=stream)
+           pair_capacity: int = 0, view_batch: int = 0, acc: Optional[torch.Tensor] = None):
+    """Algorithm 1: accumulate over all views, then Top-K (fused into the last
+    accumulation pass).  Returns (idx (N,k) int32, val (N,k) float32,
+    acc (N,M) float32, n_contrib)."""
+    dev = g.means.device
+    if acc is None:
+        acc = torch.empty((g.n, views.m_atoms), dtype=torch.float32, device=dev)
+    idx = torch.empty((g.n, k), dtype=torch.int32, device=dev)
+    val = torch.empty((g.n, k), dtype=torch.float32, device=dev)
+    nc = _uplift_call(g, views, acc, False, k, idx, val, stream, workspace, pair_capacity, view_batch)
     return idx, val, acc, nc
 
 

@@ -32,50 +32,72 @@ scoup_status fail(scoup_status s, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct UpliftLayout {
-  size_t splats, tile_count, tile_cursor, tile_start, status, keys;
-  size_t fixed;        // bytes before the key array
-  int max_tiles;
-};
-
 int tiles_of(int w, int h, int shift = 4) {
   const int t = 1 << shift;
   return ((w + t - 1) >> shift) * ((h + t - 1) >> shift);
 }
 
-UpliftLayout bin_layout(int64_t n, int max_tiles) {
-  UpliftLayout L{};
-  L.max_tiles = std::max(1, max_tiles);
+// Workspace layout of one binning pass (+ the uplift's per-view offsets and records).
+struct BinLayout {
+  size_t status, splats, offsets, scan_part, tile_start, big_tiles, radix_hist, tile_ids[2], keys[2], records,
+      total;
+};
+
+BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int rec_views) {
+  BinLayout L{};
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
   size_t off = 0;
   L.status = off; off = align256(off + sizeof(Status));
-  L.splats = off; off = align256(off + sizeof(GSplat) * (size_t)std::max<int64_t>(n, 1));
-  L.tile_count = off; off = align256(off + 4 * (size_t)L.max_tiles);
-  L.tile_cursor = off; off = align256(off + 4 * (size_t)L.max_tiles);
-  L.tile_start = off; off = align256(off + 4 * (size_t)(L.max_tiles + 1));
-  L.keys = off;
-  L.fixed = off;
+  L.splats = off; off = align256(off + sizeof(GSplat) * nn);
+  L.offsets = off; off = align256(off + 4 * (size_t)(n + 1) * (size_t)off_views);
+  const long long sparts = std::max(scan_blocks(n), scan_blocks(128 * radix_blocks(cap)));
+  L.scan_part = off; off = align256(off + 8 * (size_t)std::max<long long>(1, sparts));
+  L.tile_start = off; off = align256(off + 4 * (size_t)(max_tiles + 1));
+  L.big_tiles = off; off = align256(off + 4 * (size_t)max_tiles);
+  L.radix_hist = off; off = align256(off + 4 * 128 * (size_t)std::max<long long>(1, radix_blocks(cap)));
+  L.tile_ids[0] = off; off = align256(off + 4 * (size_t)cap);
+  L.tile_ids[1] = off; off = align256(off + 4 * (size_t)cap);
+  L.keys[0] = off; off = align256(off + 8 * (size_t)cap);
+  L.keys[1] = off; off = align256(off + 8 * (size_t)cap);
+  L.records = off; off = align256(off + 16 * (size_t)cap * (size_t)rec_views);
+  L.total = off;
   return L;
 }
 
-UpliftLayout uplift_layout(int64_t n, const scoup_views* v) {
-  int mt = 1;
-  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height));
-  return bin_layout(n, mt);
+// largest pair capacity whose single-view layout fits in `bytes` (0 if none)
+int64_t capacity_for(int64_t n, int max_tiles, size_t bytes) {
+  const size_t fixed = bin_layout(n, max_tiles, 0, 1, 0).total;
+  if (bytes <= fixed + 8192) return 0;
+  int64_t cap = (int64_t)(((bytes - fixed - 8192) * 8) / 197);
+  while (cap > 0 && bin_layout(n, max_tiles, cap, 1, 0).total > bytes) cap -= 64;
+  return std::min<int64_t>(std::max<int64_t>(cap, 0), 0x7fffffffLL);
 }
 
-void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const UpliftLayout& L, long long capacity,
+int max_tiles_of(const scoup_views* v) {
+  int mt = 1;
+  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height));
+  return mt;
+}
+
+void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const BinLayout& L, long long capacity,
               int shift, int sort_cap) {
   b.means = g->means; b.log_scales = g->log_scales; b.quats = g->quats; b.opacities = g->opacities;
   b.n = g->n;
   b.tile_shift = shift;
   b.sort_cap = sort_cap;
   b.splats = reinterpret_cast<GSplat*>(base + L.splats);
-  b.tile_count = reinterpret_cast<unsigned int*>(base + L.tile_count);
-  b.tile_cursor = reinterpret_cast<unsigned int*>(base + L.tile_cursor);
+  b.offsets = reinterpret_cast<unsigned int*>(base + L.offsets);
+  b.scan_part = reinterpret_cast<unsigned long long*>(base + L.scan_part);
   b.tile_start = reinterpret_cast<unsigned int*>(base + L.tile_start);
-  b.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
+  b.big_tiles = reinterpret_cast<unsigned int*>(base + L.big_tiles);
+  b.radix_hist = reinterpret_cast<unsigned int*>(base + L.radix_hist);
+  for (int k = 0; k < 2; ++k) {
+    b.tile_ids[k] = reinterpret_cast<unsigned int*>(base + L.tile_ids[k]);
+    b.keys[k] = reinterpret_cast<unsigned long long*>(base + L.keys[k]);
+  }
   b.capacity = capacity;
   b.status = reinterpret_cast<Status*>(base + L.status);
+  b.sorted = 0;
 }
 
 std::once_flag g_lds_once;
@@ -212,54 +234,83 @@ const char* scoup_version(void) { return "libscoup 0.1 gfx950"; }
 
 int64_t scoup_required_pair_capacity(void) { return g_required_pairs; }
 
-size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* views, int64_t pair_capacity) {
+size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* views, int64_t pair_capacity,
+                                    int32_t view_batch) {
   if (!views || n_gaussians < 0) return 0;
   if (views->n_views > 0 && !views->cams) return 0;
-  UpliftLayout L = uplift_layout(n_gaussians, views);
-  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(8 * n_gaussians, 1 << 16);
-  return L.fixed + align256(8 * (size_t)pair_capacity);
+  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(4 * n_gaussians, 1 << 16);
+  const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : views->n_views, views->n_views));
+  return bin_layout(n_gaussians, max_tiles_of(views), pair_capacity, vb, vb).total;
 }
 
-scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views* v, float* acc,
-                                     int32_t accumulate, void* ws, size_t ws_bytes,
-                                     unsigned long long* n_contrib, void* stream) {
-  g_err.clear();
+namespace {
+scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* acc, int32_t accumulate,
+                         int32_t k_top, int32_t* topk_idx, float* topk_val, int64_t pair_capacity,
+                         int32_t view_batch, void* ws, size_t ws_bytes, unsigned long long* n_contrib,
+                         void* stream) {
   scoup_status st = check_gaussians(g);
   if (st != SCOUP_OK) return st;
   if ((st = check_views(v)) != SCOUP_OK) return st;
+  if (v->region_base[v->n_views > 0 ? v->n_views : 0] > 0x7fffffffLL)
+    return fail(SCOUP_E_ARG, "more than 2^31 regions in total");
   if (g->n > 0 && !acc) return fail(SCOUP_E_ARG, "acc is NULL");
   if (!ws) return fail(SCOUP_E_ARG, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace must be 256-byte aligned");
-  const UpliftLayout L = uplift_layout(g->n, v);
-  if (ws_bytes < L.fixed + 8 * 1024) {
-    g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
-    return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
+  if (pair_capacity < 1 || pair_capacity > 0x7fffffffLL) return fail(SCOUP_E_ARG, "pair_capacity out of range");
+  const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : std::max(1, v->n_views),
+                                           std::max(1, v->n_views)));
+  const int mt = max_tiles_of(v);
+  const BinLayout L = bin_layout(g->n, mt, pair_capacity, vb, vb);
+  if (ws_bytes < L.total) {
+    g_required_pairs = pair_capacity;
+    return fail(SCOUP_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
+                                       std::to_string(L.total) + " this capacity and view batch need");
   }
-  long long capacity = (long long)((ws_bytes - L.fixed) / 8);
-  capacity = std::min<long long>(capacity, 0x7fffffffLL);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   Status* status = reinterpret_cast<Status*>(base + L.status);
   HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
-  HIP_TRY(hipMemsetAsync(base + L.tile_count, 0, 4 * (size_t)L.max_tiles, s));
   const size_t acc_bytes = sizeof(float) * (size_t)g->n * (size_t)v->m_atoms;
   if (!accumulate && acc_bytes) HIP_TRY(hipMemsetAsync(acc, 0, acc_bytes, s));
 
   UpliftViewArgs a{};
   BinArgs& b = a.bin;
-  fill_bin(b, g, base, L, capacity, 4, kSortCap);
+  fill_bin(b, g, base, L, pair_capacity, 4, kSortCap);
   a.code_idx = v->code_idx; a.code_val = v->code_val;
   a.k_code = v->k_code; a.m_atoms = v->m_atoms;
   a.acc = acc;
-  for (int i = 0; i < v->n_views; ++i) {
-    const scoup_camera& c = v->cams[i];
-    b.cam = to_dev(c);
-    b.tiles_x = (c.width + kTile - 1) / kTile;
-    b.n_tiles = tiles_of(c.width, c.height);
-    a.rmap = v->region_maps + v->map_offsets[i];
-    a.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
-    a.region_base = v->region_base[i];
-    HIP_TRY(launch_uplift_view(a, s));
+  unsigned int* off_all = b.offsets;
+  float2* rec_all = reinterpret_cast<float2*>(base + L.records);
+  RowBuildArgs rb{};
+  rb.n = g->n; rb.m_atoms = v->m_atoms; rb.k_code = v->k_code;
+  rb.code_idx = v->code_idx; rb.code_val = v->code_val;
+  rb.r_total = v->n_views > 0 ? v->region_base[v->n_views] : 0;
+  rb.offsets = off_all; rb.records = rec_all; rb.capacity = pair_capacity;
+  rb.acc = acc; rb.status = status;
+  const bool want_topk = k_top > 0;
+  if (g->n > 0) {
+    for (int v0 = 0; v0 < v->n_views; v0 += vb) {
+      const int nvb = std::min(vb, v->n_views - v0);
+      for (int j = 0; j < nvb; ++j) {
+        const int i = v0 + j;
+        const scoup_camera& c = v->cams[i];
+        b.cam = to_dev(c);
+        b.tiles_x = (c.width + kTile - 1) / kTile;
+        b.n_tiles = tiles_of(c.width, c.height);
+        b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
+        a.records = rec_all + (size_t)j * 2 * (size_t)pair_capacity;
+        a.rmap = v->region_maps + v->map_offsets[i];
+        a.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
+        a.region_base = v->region_base[i];
+        HIP_TRY(launch_uplift_view(a, s));
+      }
+      rb.n_views = nvb;
+      const bool last = v0 + vb >= v->n_views;
+      rb.k_top = (want_topk && last) ? k_top : 0;
+      rb.topk_idx = topk_idx; rb.topk_val = topk_val;
+      HIP_TRY(launch_rowbuild(rb, s));
+    }
+    if (want_topk && v->n_views == 0) HIP_TRY(launch_topk(acc, g->n, v->m_atoms, k_top, topk_idx, topk_val, s));
   }
   if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
   Status h{};
@@ -268,12 +319,21 @@ scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views
   StageTimer::collect();
   if (h.any_overflow) {
     g_required_pairs = (int64_t)h.max_pairs;
-    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(capacity) + " exceeded; need " +
+    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(pair_capacity) + " exceeded; need " +
                                        std::to_string(h.max_pairs));
   }
   if (h.data_error & 1u) return fail(SCOUP_E_DATA, "a region id is outside [-1, regions of its view)");
   if (h.data_error & 2u) return fail(SCOUP_E_DATA, "a code atom index is >= m_atoms");
   return SCOUP_OK;
+}
+}  // namespace
+
+scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views* v, float* acc,
+                                     int32_t accumulate, int64_t pair_capacity, int32_t view_batch, void* ws,
+                                     size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  return uplift_impl(g, v, acc, accumulate, 0, nullptr, nullptr, pair_capacity, view_batch, ws, ws_bytes,
+                     n_contrib, stream);
 }
 
 scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k, int32_t* idx, float* val,
@@ -291,22 +351,21 @@ scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k, int32
 }
 
 scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* v, int32_t k, float* acc,
-                          int32_t* topk_idx, float* topk_val, void* ws, size_t ws_bytes,
-                          unsigned long long* n_contrib, void* stream) {
+                          int32_t* topk_idx, float* topk_val, int64_t pair_capacity, int32_t view_batch, void* ws,
+                          size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
   g_err.clear();
   if (!v) return fail(SCOUP_E_ARG, "views is NULL");
   if (k < 1 || k > 64 || k > v->m_atoms) return fail(SCOUP_E_ARG, "k must be in [1, min(64, m_atoms)]");
   if (v->m_atoms > 4096) return fail(SCOUP_E_ARG, "m_atoms must be <= 4096");
-  scoup_status st = scoup_uplift_accumulate(g, v, acc, 0, ws, ws_bytes, n_contrib, stream);
-  if (st != SCOUP_OK) return st;
-  return scoup_topk(acc, g->n, v->m_atoms, k, topk_idx, topk_val, stream);
+  if (g && g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
+  return uplift_impl(g, v, acc, 0, k, topk_idx, topk_val, pair_capacity, view_batch, ws, ws_bytes, n_contrib,
+                     stream);
 }
 
 size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int64_t pair_capacity) {
   if (!cam || n_gaussians < 0) return 0;
-  UpliftLayout L = bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3));
-  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(16 * n_gaussians, 1 << 16);
-  return L.fixed + align256(8 * (size_t)pair_capacity);
+  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(8 * n_gaussians, 1 << 16);
+  return bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3), pair_capacity, 1, 0).total;
 }
 
 scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
@@ -328,12 +387,13 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
   HIP_TRY(ensure_lds_limits());
   const int shift = 3;
-  const UpliftLayout L = bin_layout(g->n, tiles_of(cam->width, cam->height, shift));
-  if (ws_bytes < L.fixed + 8 * 1024) {
-    g_required_pairs = std::max<int64_t>(16 * g->n, 1 << 16);
+  const int mt = tiles_of(cam->width, cam->height, shift);
+  const long long capacity = capacity_for(g->n, mt, ws_bytes);
+  if (capacity < 1) {
+    g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
   }
-  long long capacity = std::min<long long>((long long)((ws_bytes - L.fixed) / 8), 0x7fffffffLL);
+  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   RenderViewArgs a{};
@@ -342,12 +402,11 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   a.bin.sort_cap = sort_cap;
   a.bin.cam = to_dev(*cam);
   a.bin.tiles_x = (cam->width + 7) / 8;
-  a.bin.n_tiles = tiles_of(cam->width, cam->height, shift);
+  a.bin.n_tiles = mt;
   a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
   a.out_dtype = coeff_dtype; a.out = coeff_map; a.out_scale = coeff_scale; a.t_final = t_final;
   Status* status = a.bin.status;
   HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
-  HIP_TRY(hipMemsetAsync(base + L.tile_count, 0, 4 * (size_t)L.max_tiles, s));
   HIP_TRY(launch_render_view(a, s));
   if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
   Status h{};
@@ -431,17 +490,18 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   const size_t prep_b = align256(decode_codebook_bytes(dim, m_atoms, SCOUP_F32));
   const size_t dw_b = align256(4 * (size_t)P * m_atoms);
   const int shift = 3;
-  const UpliftLayout L = bin_layout(g->n, tiles_of(cam->width, cam->height, shift));
-  if (ws_bytes < prep_b + dw_b + L.fixed + 8 * 1024) {
-    g_required_pairs = std::max<int64_t>(16 * g->n, 1 << 16);
+  const int mt = tiles_of(cam->width, cam->height, shift);
+  if (ws_bytes < prep_b + dw_b) return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
+  const long long capacity = capacity_for(g->n, mt, ws_bytes - prep_b - dw_b);
+  if (capacity < 1) {
+    g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
   }
+  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0);
   char* base = static_cast<char*>(ws);
   void* prep = base;
   float* dW = reinterpret_cast<float*>(base + prep_b);
   char* bbase = base + prep_b + dw_b;
-  long long capacity =
-      std::min<long long>((long long)((ws_bytes - prep_b - dw_b - L.fixed) / 8), 0x7fffffffLL);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // dW = G C^T : K = dim, N = m_atoms, B(k, n) = C[n * dim + k]
   HIP_TRY(launch_prep_codebook(codebook, dim, m_atoms, SCOUP_F32, prep, nullptr, s, 1));
@@ -458,12 +518,11 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   a.bin.sort_cap = sort_cap;
   a.bin.cam = to_dev(*cam);
   a.bin.tiles_x = (cam->width + 7) / 8;
-  a.bin.n_tiles = tiles_of(cam->width, cam->height, shift);
+  a.bin.n_tiles = mt;
   a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
   a.dW = dW; a.grad_val = grad_topk_val;
   Status* status = a.bin.status;
   HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
-  HIP_TRY(hipMemsetAsync(bbase + L.tile_count, 0, 4 * (size_t)L.max_tiles, s));
   HIP_TRY(launch_render_bwd_view(a, s));
   Status h{};
   HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));

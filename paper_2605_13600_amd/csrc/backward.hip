@@ -159,13 +159,13 @@ hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int
   return hipGetLastError();
 }
 
-hipError_t launch_render_bwd_view(const RenderBwdArgs& a, hipStream_t s) {
+hipError_t launch_render_bwd_view(RenderBwdArgs& a, hipStream_t s) {
   hipError_t e = launch_bin_view(a.bin, s);
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   const size_t lds = sizeof(float) * 64 * (size_t)(a.m_atoms + 1);
   StageTimer::begin(kStRenderBwd, s);
-  hipLaunchKernelGGL(k_render_bwd, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start, b.keys,
+  hipLaunchKernelGGL(k_render_bwd, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start, b.keys[b.sorted],
                      b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.k, a.m_atoms, b.sort_cap, a.dW,
                      a.grad_val, b.status);
   StageTimer::end(kStRenderBwd, s);

@@ -1,0 +1,451 @@
+// Projection and tile binning shared by the uplift, the render and the
+// backward (Sec. 3: the 3DGS tile rasterizer whose blending weights feed
+// Eq. 1-2; Eq. 1's "ordered from front to back").  No global atomics:
+//
+//   k_project     one thread per Gaussian: FP64 EWA projection -> GSplat,
+//                 number of overlapped tiles n_i
+//   scan          device-wide exclusive scan of n_i -> Gaussian-major pair
+//                 offsets off_i (also the record slots of the uplift)
+//   k_emit        pair (i, t) at off_i + (row-major index of t in i's rect):
+//                 tile id + key (float32 depth bits << 32 | i)
+//   radix         stable LSD radix sort of the pairs by tile id (7-bit digits)
+//   k_tile_ranges tile t owns sorted pairs [tile_start[t], tile_start[t+1])
+//   k_sort_big    tiles longer than the consumer's LDS sort are sorted by
+//                 (depth, id) here; shorter ones are sorted in LDS by the consumer
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "scoup_device.h"
+#include "scoup_internal.h"
+
+namespace scoup {
+
+// ---------------------------------------------------------------------------
+// projection (one thread per Gaussian), FP64 arithmetic, FP32 storage
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_project(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ opacities, long long n,
+    CamDev cam, int tile_shift, GSplat* __restrict__ out, unsigned int* __restrict__ n_tiles) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  GSplat s;
+  s.ix = 0; s.iy = 0; s.fx = 0.f; s.fy = 0.f;
+  s.l00 = 0.f; s.l10 = 0.f; s.l11 = 0.f; s.opacity = 0.f;
+  s.bx0 = 1; s.bx1 = 0; s.by0 = 1; s.by1 = 0;   // empty box = invisible
+  s.depth_bits = 0u; s.pad = 0u;
+  unsigned int nt = 0;
+
+  const double mx = means[3 * i + 0], my = means[3 * i + 1], mz = means[3 * i + 2];
+  double x, y, z;
+  {
+    // Camera point p = R mu + t summed left to right without fused multiply-adds,
+    // so the view depth (and its float32 sort key) is reproducible exactly.
+#pragma clang fp contract(off)
+    x = (double)cam.R[0] * mx + (double)cam.R[1] * my + (double)cam.R[2] * mz + (double)cam.t[0];
+    y = (double)cam.R[3] * mx + (double)cam.R[4] * my + (double)cam.R[5] * mz + (double)cam.t[1];
+    z = (double)cam.R[6] * mx + (double)cam.R[7] * my + (double)cam.R[8] * mz + (double)cam.t[2];
+  }
+  const double o = opacities[i];
+  const double lo = log(255.0 * o);
+  if (!(z > (double)cam.near_z) || !(lo >= 0.0)) { out[i] = s; n_tiles[i] = 0u; return; }
+
+  // 3D covariance Sigma = R diag(exp(2 s)) R^T from the normalised quaternion
+  double qw = quats[4 * i + 0], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+  const double Rq[3][3] = {
+      {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+      {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
+      {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
+  const double s2[3] = {exp(2.0 * (double)log_scales[3 * i + 0]),
+                        exp(2.0 * (double)log_scales[3 * i + 1]),
+                        exp(2.0 * (double)log_scales[3 * i + 2])};
+  double S[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      S[a][b] = Rq[a][0] * s2[0] * Rq[b][0] + Rq[a][1] * s2[1] * Rq[b][1] + Rq[a][2] * s2[2] * Rq[b][2];
+
+  // EWA Jacobian at the clamped camera point
+  const double fx = cam.fx, fy = cam.fy;
+  const double limx = 1.3 * ((double)cam.width / (2.0 * fx));
+  const double limy = 1.3 * ((double)cam.height / (2.0 * fy));
+  const double tx = fmin(limx, fmax(-limx, x / z)) * z;
+  const double ty = fmin(limy, fmax(-limy, y / z)) * z;
+  const double j00 = fx / z, j02 = -fx * tx / (z * z);
+  const double j11 = fy / z, j12 = -fy * ty / (z * z);
+  double T0[3], T1[3];   // T = J W, W the camera rotation
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    T0[b] = j00 * (double)cam.R[0 * 3 + b] + j02 * (double)cam.R[2 * 3 + b];
+    T1[b] = j11 * (double)cam.R[1 * 3 + b] + j12 * (double)cam.R[2 * 3 + b];
+  }
+  double U0[3], U1[3];   // T Sigma
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    U0[b] = T0[0] * S[0][b] + T0[1] * S[1][b] + T0[2] * S[2][b];
+    U1[b] = T1[0] * S[0][b] + T1[1] * S[1][b] + T1[2] * S[2][b];
+  }
+  const double sxx = U0[0] * T0[0] + U0[1] * T0[1] + U0[2] * T0[2] + 0.3;
+  const double sxy = U0[0] * T1[0] + U0[1] * T1[1] + U0[2] * T1[2];
+  const double syy = U1[0] * T1[0] + U1[1] * T1[1] + U1[2] * T1[2] + 0.3;
+  const double det = sxx * syy - sxy * sxy;
+  const double mux = fx * x / z + (double)cam.cx;
+  const double muy = fy * y / z + (double)cam.cy;
+  if (!(det > 0.0) || !(fabs(mux) < 1073741824.0) || !(fabs(muy) < 1073741824.0)) {
+    out[i] = s; n_tiles[i] = 0u; return;
+  }
+  // conservative pixel box of {alpha >= 1/255}: |dx| <= sqrt(2 ln(255 o) Sxx)
+  const double r2 = 2.0 * lo;
+  const double hx = sqrt(r2 * sxx), hy = sqrt(r2 * syy);
+  double x0 = ceil(mux - hx - 0.5) - 1.0, x1 = floor(mux + hx - 0.5) + 1.0;
+  double y0 = ceil(muy - hy - 0.5) - 1.0, y1 = floor(muy + hy - 0.5) + 1.0;
+  x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+  x1 = fmin(x1, (double)(cam.width - 1)); y1 = fmin(y1, (double)(cam.height - 1));
+  if (!(x0 <= x1) || !(y0 <= y1)) { out[i] = s; n_tiles[i] = 0u; return; }
+
+  // scaled factor of the conic: q = (l00 dx + l10 dy)^2 + (l11 dy)^2 = log2(e)/2 d^T conic d
+  const double ks = 0.84932180028801904272;   // sqrt(log2(e) / 2)
+  const double l00 = sqrt(syy / det), l10 = -sxy / sqrt(det * syy), l11 = 1.0 / sqrt(syy);
+  const double flx = floor(mux), fly = floor(muy);
+  s.ix = (int)flx; s.iy = (int)fly;
+  s.fx = (float)(mux - flx); s.fy = (float)(muy - fly);
+  if (s.fx >= 1.0f) { s.fx = 0.0f; s.ix += 1; }
+  if (s.fy >= 1.0f) { s.fy = 0.0f; s.iy += 1; }
+  s.l00 = (float)(l00 * ks); s.l10 = (float)(l10 * ks); s.l11 = (float)(l11 * ks);
+  s.opacity = (float)o;
+  s.bx0 = (int16_t)x0; s.bx1 = (int16_t)x1; s.by0 = (int16_t)y0; s.by1 = (int16_t)y1;
+  s.depth_bits = __float_as_uint((float)z);
+  out[i] = s;
+  nt = (unsigned int)(((s.bx1 >> tile_shift) - (s.bx0 >> tile_shift) + 1) *
+                      ((s.by1 >> tile_shift) - (s.by0 >> tile_shift) + 1));
+  n_tiles[i] = nt;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan of n unsigned values, in place, in three kernels
+// (block sums, scan of the sums, block-local scan + offset).  2048 per block.
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__device__ __forceinline__ unsigned long long block_exclusive_scan_256(unsigned long long v,
+                                                                        unsigned long long* sh,
+                                                                        unsigned long long* total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const unsigned long long a = tid >= o ? sh[tid - o] : 0ull;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  const unsigned long long incl = sh[tid];
+  *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const unsigned int* __restrict__ in, long long n,
+                                                     unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long sh[256];
+  const long long b0 = (long long)blockIdx.x * kScanBlock;
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long i = b0 + (long long)k * 256 + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// one workgroup: exclusive scan of the block sums, total pairs and capacity check
+__global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* __restrict__ part, int nb,
+                                                   unsigned long long capacity, Status* st) {
+  __shared__ unsigned long long sh[1024];
+  const int tid = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b = tid * per, e = min(nb, b + per);
+  unsigned long long s = 0;
+  for (int i = b; i < e; ++i) s += part[i];
+  sh[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned long long a = tid >= o ? sh[tid - o] : 0ull;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  unsigned long long run = sh[tid] - s;
+  const unsigned long long total = sh[1023];
+  for (int i = b; i < e; ++i) {
+    const unsigned long long v = part[i];
+    part[i] = run;
+    run += v;
+  }
+  if (tid == 0 && st) {
+    st->n_big = 0u;
+    const bool over = total > capacity;
+    st->total_pairs = over ? 0u : (unsigned int)total;
+    st->view_overflow = over ? 1u : 0u;
+    if (over) st->any_overflow = 1u;
+    const unsigned int t32 = total > 0xffffffffull ? 0xffffffffu : (unsigned int)total;
+    if (t32 > st->max_pairs) st->max_pairs = t32;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(unsigned int* __restrict__ data, long long n,
+                                                   const unsigned long long* __restrict__ part,
+                                                   unsigned int* __restrict__ total_out) {
+  __shared__ unsigned long long sh[256];
+  const long long b0 = (long long)blockIdx.x * kScanBlock;
+  // each thread owns kScanItems consecutive elements
+  const long long i0 = b0 + (long long)threadIdx.x * kScanItems;
+  unsigned int v[kScanItems];
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (i0 + k < n) ? data[i0 + k] : 0u;
+    s += v[k];
+  }
+  unsigned long long tot;
+  unsigned long long run = block_exclusive_scan_256(s, sh, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (i0 + k < n) data[i0 + k] = (unsigned int)run;
+    run += v[k];
+  }
+  if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total_out = (unsigned int)run;
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian-major pair emission
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n, int tiles_x,
+                                              int tile_shift, const unsigned int* __restrict__ off,
+                                              unsigned int* __restrict__ tile_ids,
+                                              unsigned long long* __restrict__ keys, const Status* st) {
+  if (st->view_overflow) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const GSplat s = splats[i];
+  if (s.bx0 > s.bx1) return;
+  const unsigned long long key = ((unsigned long long)s.depth_bits << 32) | (unsigned long long)i;
+  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
+  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
+  unsigned int p = off[i];
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx, ++p) {
+      tile_ids[p] = (unsigned int)(ty * tiles_x + tx);
+      keys[p] = key;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (tile id, key) pairs by tile id, 7-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kRadixBits = 7;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixItems = 16;                   // per thread
+constexpr int kRadixBlock = 256 * kRadixItems;    // per workgroup
+
+__global__ __launch_bounds__(256) void k_radix_hist(const unsigned int* __restrict__ tid_in, int shift,
+                                                    int nblocks, unsigned int* __restrict__ hist,
+                                                    const Status* st) {
+  __shared__ unsigned int h[kRadixBins];
+  if (st->view_overflow) return;
+  const long long n = st->total_pairs;
+  if (threadIdx.x < kRadixBins) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const long long b0 = (long long)blockIdx.x * kRadixBlock;
+#pragma unroll
+  for (int k = 0; k < kRadixItems; ++k) {
+    const long long i = b0 + (long long)k * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&h[(tid_in[i] >> shift) & (kRadixBins - 1)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kRadixBins) hist[(long long)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Rounds of 256 consecutive elements; inside a round the order is wave-major,
+// lane-minor, so a stable rank is: running digit offset of the block + same-
+// digit elements of earlier waves in the round + same-digit earlier lanes.
+__global__ __launch_bounds__(256) void k_radix_scatter(const unsigned int* __restrict__ tid_in,
+                                                       const unsigned long long* __restrict__ key_in, int shift,
+                                                       int nblocks, const unsigned int* __restrict__ hist,
+                                                       unsigned int* __restrict__ tid_out,
+                                                       unsigned long long* __restrict__ key_out,
+                                                       const Status* st) {
+  __shared__ unsigned int run[kRadixBins];
+  __shared__ unsigned int wcnt[4][kRadixBins];
+  if (st->view_overflow) return;
+  const long long n = st->total_pairs;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < kRadixBins) run[tid] = hist[(long long)tid * nblocks + blockIdx.x];
+  for (int j = tid; j < 4 * kRadixBins; j += 256) (&wcnt[0][0])[j] = 0u;
+  __syncthreads();
+  const long long b0 = (long long)blockIdx.x * kRadixBlock;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRadixItems; ++r) {
+    const long long i = b0 + (long long)r * 256 + tid;
+    const bool valid = i < n;
+    unsigned int t = 0;
+    unsigned long long kv = 0;
+    if (valid) { t = tid_in[i]; kv = key_in[i]; }
+    const unsigned int d = (t >> shift) & (kRadixBins - 1);
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      const unsigned long long bb = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    const unsigned int inwave = (unsigned int)__popcll(peers & lt);
+    if (valid && inwave == 0) wcnt[wave][d] = (unsigned int)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      unsigned int before = 0;
+      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+      const unsigned int pos = run[d] + before + inwave;
+      tid_out[pos] = t;
+      key_out[pos] = kv;
+    }
+    __syncthreads();
+    if (tid < kRadixBins) {
+      run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+      wcnt[0][tid] = 0u; wcnt[1][tid] = 0u; wcnt[2][tid] = 0u; wcnt[3][tid] = 0u;
+    }
+    __syncthreads();
+  }
+}
+
+// tile_start[t] = first sorted pair with tile id >= t (t = 0..n_tiles); tiles
+// longer than sort_cap are appended to big_tiles for k_sort_big
+__global__ __launch_bounds__(256) void k_tile_ranges(const unsigned int* __restrict__ tile_ids, int n_tiles,
+                                                     unsigned int* __restrict__ tile_start, int sort_cap,
+                                                     unsigned int* __restrict__ big_tiles, Status* st) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n_tiles) return;
+  const unsigned int n = st->view_overflow ? 0u : st->total_pairs;
+  auto lower = [&](unsigned int x) {
+    unsigned int lo = 0, hi = n;
+    while (lo < hi) {
+      const unsigned int mid = (lo + hi) >> 1;
+      if (tile_ids[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  const unsigned int a = lower((unsigned int)t);
+  tile_start[t] = a;
+  if (t < n_tiles) {
+    const unsigned int b = lower((unsigned int)t + 1u);
+    if (b - a > (unsigned int)sort_cap) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
+  }
+}
+
+// Tiles whose list exceeds the consumer's LDS sort capacity are sorted in
+// place in global memory, one workgroup per listed tile (rare; correctness
+// path for dense tiles).  A small fixed grid walks the list.
+__global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restrict__ keys,
+                                                   const unsigned int* __restrict__ tile_start,
+                                                   const unsigned int* __restrict__ big_tiles, const Status* st) {
+  if (st->view_overflow) return;
+  const unsigned int nbig = st->n_big;
+  const int tid = threadIdx.x;
+  for (unsigned int q = blockIdx.x; q < nbig; q += gridDim.x) {
+    const unsigned int tile = big_tiles[q];
+    const unsigned int start = tile_start[tile];
+    const long long L = (long long)tile_start[tile + 1] - start;
+    unsigned long long* s = keys + start;
+    long long n2 = 1;
+    while (n2 < L) n2 <<= 1;
+    for (long long k = 2; k <= n2; k <<= 1) {
+      const long long hk = k >> 1;
+      for (long long i = tid; i < (n2 >> 1); i += 1024) {
+        const long long blk = i / hk, off = i - blk * hk;
+        const long long a = blk * k + off, b = blk * k + k - 1 - off;
+        if (b < L) cmp_swap(&s[a], &s[b]);
+      }
+      __syncthreads();
+      for (long long j = k >> 2; j >= 1; j >>= 1) {
+        for (long long i = tid; i < (n2 >> 1); i += 1024) {
+          const long long blk = i / j, off = i - blk * j;
+          const long long a = blk * 2 * j + off, b = a + j;
+          if (b < L) cmp_swap(&s[a], &s[b]);
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int radix_passes(int n_tiles) {
+  int bits = 1;
+  while ((1 << bits) < n_tiles) ++bits;
+  return (bits + kRadixBits - 1) / kRadixBits;
+}
+
+long long radix_blocks(long long capacity) { return (capacity + kRadixBlock - 1) / kRadixBlock; }
+long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
+  const int nb = (int)((a.n + 255) / 256);
+  if (a.n > 0) {
+    StageTimer::begin(kStProject, s);
+    hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, s, a.means, a.log_scales, a.quats, a.opacities,
+                       a.n, a.cam, a.tile_shift, a.splats, a.offsets);
+    StageTimer::end(kStProject, s);
+  }
+  StageTimer::begin(kStScan, s);
+  const int sb = (int)scan_blocks(a.n);
+  if (sb > 0)
+    hipLaunchKernelGGL(k_scan_reduce, dim3(sb), dim3(256), 0, s, a.offsets, a.n, a.scan_part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.scan_part, sb,
+                     (unsigned long long)a.capacity, a.status);
+  if (sb > 0)
+    hipLaunchKernelGGL(k_scan_down, dim3(sb), dim3(256), 0, s, a.offsets, a.n, a.scan_part, a.offsets + a.n);
+  StageTimer::end(kStScan, s);
+  if (a.n > 0) {
+    StageTimer::begin(kStEmit, s);
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_shift, a.offsets,
+                       a.tile_ids[0], a.keys[0], a.status);
+    StageTimer::end(kStEmit, s);
+  }
+  // radix sort by tile id: passes alternate between the two buffers
+  StageTimer::begin(kStSortBig, s);
+  const int passes = radix_passes(a.n_tiles);
+  const int rb = (int)radix_blocks(a.capacity);
+  const long long hlen = (long long)rb * kRadixBins;
+  const int hsb = (int)scan_blocks(hlen);
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3(rb), dim3(256), 0, s, a.tile_ids[cur], shift, rb, a.radix_hist,
+                       a.status);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(hsb), dim3(256), 0, s, a.radix_hist, hlen, a.scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.scan_part, hsb, 0ull, (Status*)nullptr);
+    hipLaunchKernelGGL(k_scan_down, dim3(hsb), dim3(256), 0, s, a.radix_hist, hlen, a.scan_part,
+                       (unsigned int*)nullptr);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(rb), dim3(256), 0, s, a.tile_ids[cur], a.keys[cur], shift, rb,
+                       a.radix_hist, a.tile_ids[cur ^ 1], a.keys[cur ^ 1], a.status);
+    cur ^= 1;
+  }
+  a.sorted = cur;
+  hipLaunchKernelGGL(k_tile_ranges, dim3((a.n_tiles + 1 + 255) / 256), dim3(256), 0, s, a.tile_ids[cur],
+                     a.n_tiles, a.tile_start, a.sort_cap, a.big_tiles, a.status);
+  hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[cur], a.tile_start, a.big_tiles,
+                     a.status);
+  StageTimer::end(kStSortBig, s);
+  return hipGetLastError();
+}
+
+}  // namespace scoup

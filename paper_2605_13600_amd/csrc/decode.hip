@@ -10,6 +10,8 @@
 // Wave w owns pixels [64 (w/4), +64) and columns [(w%4) D/4, +D/4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "scoup_device.h"
 #include "scoup_internal.h"
 
@@ -60,21 +62,30 @@ __global__ __launch_bounds__(256) void k_prep_codebook(const float* __restrict__
   }
 }
 
-// power-of-two scale s with max|C| s <= 448 (FP8 E4M3 range), one workgroup
-__global__ __launch_bounds__(256) void k_fp8_scale(const float* __restrict__ C, long long n, float* scale) {
+// max |C| as float bits (non-negative floats order like their bit patterns)
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ C, long long n,
+                                                unsigned int* __restrict__ maxbits) {
   __shared__ float red[256];
   float m = 0.0f;
-  for (long long i = threadIdx.x; i < n; i += 256) m = fmaxf(m, fabsf(C[i]));
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    m = fmaxf(m, fabsf(C[i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const float mx = red[0];
-    scale[0] = mx > 0.0f ? exp2f(floorf(log2f(448.0f / mx))) : 1.0f;
-  }
+  if (threadIdx.x == 0) atomicMax(maxbits, __float_as_uint(red[0]));
+}
+
+// power-of-two scale s with max|C| s <= 448 (FP8 E4M3 range)
+__device__ __forceinline__ float fp8_scale_from(unsigned int maxbits) {
+  const float mx = __uint_as_float(maxbits);
+  return mx > 0.0f ? exp2f(floorf(log2f(448.0f / mx))) : 1.0f;
+}
+
+__global__ void k_fp8_scale(const unsigned int* __restrict__ maxbits, float* scale) {
+  scale[0] = fp8_scale_from(*maxbits);
 }
 
 __device__ __forceinline__ void store_f(float* p, float v) { *p = v; }
@@ -253,7 +264,12 @@ hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void
   const long long total = (long long)(npad / 32) * (kpad / ks) * 64;
   const int grid = (int)((total + 255) / 256);
   if (in_dtype == SCOUP_FP8_E4M3) {
-    hipLaunchKernelGGL(k_fp8_scale, dim3(1), dim3(256), 0, s, C, (long long)m * d, scale);
+    unsigned int* maxbits = reinterpret_cast<unsigned int*>(scale + 1);
+    hipMemsetAsync(maxbits, 0, sizeof(unsigned int), s);
+    const long long n = (long long)m * d;
+    const int gb = (int)std::min<long long>(256, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax, dim3(gb), dim3(256), 0, s, C, n, maxbits);
+    hipLaunchKernelGGL(k_fp8_scale, dim3(1), dim3(1), 0, s, (const unsigned int*)maxbits, scale);
     hipLaunchKernelGGL(k_prep_codebook<SCOUP_FP8_E4M3>, dim3(grid), dim3(256), 0, s, C, m, d, kpad, npad,
                        transposed, (uint8_t*)out, (const float*)scale);
   } else if (in_dtype == SCOUP_BF16) {

@@ -91,9 +91,9 @@ __global__ __launch_bounds__(64) void k_render_coeff(
       }
       if (e > 0.0f) {
         ++count;
-        for (int kk = 0; kk < K; ++kk) {
+        for (int kk = 0; kk < K; ++kk) {   // fire-and-forget LDS adds: no read-modify-write chain
           const int jj = s_ti[k * K + kk];
-          if (jj >= 0 && jj < M) myrow[jj] += e * s_tv[k * K + kk];
+          if (jj >= 0 && jj < M) atomicAdd(&myrow[jj], e * s_tv[k * K + kk]);
           else if (jj >= M) atomicOr(&st->data_error, 4u);
         }
       }
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64) void k_render_coeff(
   }
 }
 
-hipError_t launch_render_view(const RenderViewArgs& a, hipStream_t s) {
+hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
   hipError_t e = launch_bin_view(a.bin, s);
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
@@ -124,18 +124,18 @@ hipError_t launch_render_view(const RenderViewArgs& a, hipStream_t s) {
   switch (a.out_dtype) {
     case SCOUP_F32:
       hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start,
-                         b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
+                         b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
                          a.m_atoms, b.sort_cap, (float*)a.out, a.out_scale, a.t_final, b.status);
       break;
     case SCOUP_BF16:
       hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
-                         b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint16_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;
     default:
       hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
-                         b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint8_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;

@@ -40,7 +40,8 @@ struct Status {
   unsigned int any_overflow;
   unsigned int max_pairs;       // largest per-view pair count seen
   unsigned int data_error;      // region id out of range
-  unsigned int pad[3];
+  unsigned int n_big;           // tiles of the current view sorted in global memory
+  unsigned int pad[2];
   unsigned long long contrib;   // contributions composited
 };
 
@@ -52,19 +53,55 @@ struct CamDev {
   float near_z;
 };
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Sum over the 64 lanes of a wave, the same value returned to every lane.
+// DPP within rows of 16 (xor 1, xor 2 via quad permutes, rotate 4 and 8),
+// then the four row sums are read from lanes 0, 16, 32, 48 (fixed order).
+template <int CTRL>
+__device__ __forceinline__ float dpp_shuffle(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_shuffle<0xb1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_shuffle<0x4e>(v);    // quad_perm [2,3,0,1]
+  v += dpp_shuffle<0x124>(v);   // row_ror:4
+  v += dpp_shuffle<0x128>(v);   // row_ror:8
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned int dpp_u32(unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void max_step_u64(unsigned int& hi, unsigned int& lo) {
+  const unsigned int h2 = dpp_u32<CTRL>(hi), l2 = dpp_u32<CTRL>(lo);
+  const bool take = h2 > hi || (h2 == hi && l2 > lo);
+  hi = take ? h2 : hi;
+  lo = take ? l2 : lo;
+}
+
+// Maximum over the 64 lanes of a wave of a 64-bit key, returned to every lane.
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  unsigned int hi = (unsigned int)(v >> 32), lo = (unsigned int)v;
+  max_step_u64<0xb1>(hi, lo);
+  max_step_u64<0x4e>(hi, lo);
+  max_step_u64<0x124>(hi, lo);
+  max_step_u64<0x128>(hi, lo);
+  unsigned long long best = 0ull;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    unsigned long long w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned int h = (unsigned int)__builtin_amdgcn_readlane((int)hi, 16 * r);
+    const unsigned int l = (unsigned int)__builtin_amdgcn_readlane((int)lo, 16 * r);
+    const unsigned long long k = ((unsigned long long)h << 32) | l;
+    best = k > best ? k : best;
   }
-  return v;
+  return best;
 }
 
 // float32 -> bfloat16, round to nearest even (NaN kept quiet).

@@ -8,7 +8,7 @@
 namespace scoup {
 
 enum Stage { kStProject = 0, kStScan, kStEmit, kStSortBig, kStComposite, kStTopk, kStRender, kStDecode,
-             kStRenderBwd, kStBwdGemm, kNumStages };
+             kStRenderBwd, kStBwdGemm, kStRowBuild, kNumStages };
 
 // Records a HIP event pair around each launch when stage timing is enabled.
 struct StageTimer {
@@ -29,15 +29,25 @@ struct BinArgs {
   int tile_shift;          // tile edge = 1 << tile_shift pixels
   int tiles_x, n_tiles;
   int sort_cap;            // tiles with longer lists are sorted in global memory
-  GSplat* splats;
-  unsigned int* tile_count;
-  unsigned int* tile_cursor;
-  unsigned int* tile_start;
-  unsigned long long* keys;
+  GSplat* splats;          // [n]
+  unsigned int* offsets;   // [n+1] Gaussian-major pair offsets (exclusive scan of tile counts)
+  unsigned long long* scan_part;   // [scan blocks]
+  unsigned int* tile_ids[2];       // [capacity] x 2
+  unsigned long long* keys[2];     // [capacity] x 2, depth bits << 32 | gaussian id
+  unsigned int* radix_hist;        // [128 * radix blocks]
+  unsigned int* tile_start;        // [n_tiles + 1]
+  unsigned int* big_tiles;         // [n_tiles] tiles longer than sort_cap
   long long capacity;
   Status* status;
+  int sorted;              // set by launch_bin_view: which buffer holds the sorted pairs
 };
 
+hipError_t launch_bin_view(BinArgs& a, hipStream_t s);
+int radix_passes(int n_tiles);
+long long radix_blocks(long long capacity);
+long long scan_blocks(long long n);
+
+// One view of the uplift: composite + per-(Gaussian, tile) region records.
 struct UpliftViewArgs {
   BinArgs bin;
   const int* rmap;
@@ -46,10 +56,29 @@ struct UpliftViewArgs {
   const int* code_idx;
   const float* code_val;
   int k_code, m_atoms;
-  float* acc;
+  float* acc;              // regions beyond a tile's two record slots go here directly
+  float2* records;         // [2 * capacity] (global region id as int bits, weight) of this view
 };
+hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s);
 
-hipError_t launch_bin_view(const BinArgs& a, hipStream_t s);
+// Sum the records of a batch of views into the accumulator rows (and Top-K).
+struct RowBuildArgs {
+  long long n;
+  int m_atoms, k_code;
+  const int* code_idx;
+  const float* code_val;
+  long long r_total;               // code table rows; records naming others are ignored
+  int n_views;                     // views in the batch
+  const unsigned int* offsets;     // [n_views][n+1]
+  const float2* records;           // [n_views][2 * capacity]
+  long long capacity;
+  float* acc;
+  int k_top;                       // 0: no Top-K
+  int* topk_idx;
+  float* topk_val;
+  Status* status;
+};
+hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s);
 
 struct RenderViewArgs {
   BinArgs bin;
@@ -61,7 +90,7 @@ struct RenderViewArgs {
   float out_scale;
   float* t_final;
 };
-hipError_t launch_render_view(const RenderViewArgs& a, hipStream_t s);
+hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s);
 hipError_t render_set_lds_limits();
 
 struct DecodeArgs {
@@ -90,7 +119,7 @@ struct RenderBwdArgs {
   const float* dW;             // [P x m] float32 gradient of the coefficient map
   float* grad_val;             // [N x k] float32, accumulated
 };
-hipError_t launch_render_bwd_view(const RenderBwdArgs& a, hipStream_t s);
+hipError_t launch_render_bwd_view(RenderBwdArgs& a, hipStream_t s);
 hipError_t render_bwd_set_lds_limits();
 // grad_C[m x d] += coeff^T [m x P] * G [P x d], float32 MFMA, split over pixels
 hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int m, int d, float* grad_C,

@@ -1,239 +1,46 @@
-// Uplift path of libscoup: projection, tile binning, per-tile depth sort,
-// front-to-back compositing fused with the weighted sparse accumulation, and
-// the per-row Top-K filter.  gfx950 (CDNA4), wave64.
+// Uplift path of libscoup: front-to-back compositing fused with the weighted
+// sparse accumulation, the per-Gaussian row build across views, and Top-K.
+// gfx950 (CDNA4), wave64.
 //
 // Paper mapping:
-//   k_project        Sec. 3 (3DGS Gaussians, EWA splat of the tile rasterizer
-//                    that produces alpha_i = o_i G_i^2D of Eq. 2)
-//   k_tile_scan,
-//   k_emit, sort     tile binning and front-to-back order of N_{v,p} (Eq. 1)
-//   k_composite_acc  Eq. 2 weights e = alpha T, then Eq. 5 / Algorithm 1:
-//                    w_i[j] += c_j e_i(v,p) for each code slot of the pixel's region
-//   k_topk           Eq. 6 Top-K and L1 normalisation
+//   k_composite_rec  Eq. 2 weights e = alpha T on one 16x16 tile, reduced per
+//                    (Gaussian, tile region) -- the pixels of a region share one
+//                    code (Sec. 4.1), so Algorithm 1's inner loop collapses to
+//                    one weight per (Gaussian, region) touch.  The first two
+//                    regions of a tile go to fixed record slots of the
+//                    (Gaussian, tile) pair; further regions are added to the
+//                    accumulator with atomics.
+//   k_rowbuild       Eq. 5 / Algorithm 1: w_i[j] += c_j * weight for every
+//                    record of Gaussian i over a batch of views, in LDS; rows
+//                    written once, coalesced; Eq. 6 Top-K fused on the last batch.
+//   k_topk           Eq. 6 on an accumulator in memory.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 
 #include "scoup_device.h"
 #include "scoup_internal.h"
 
 namespace scoup {
 
-// ---------------------------------------------------------------------------
-// projection (one thread per Gaussian), FP64 arithmetic, FP32 storage
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_project(
-    const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ opacities, long long n,
-    CamDev cam, int tiles_x, int tile_shift, GSplat* __restrict__ out,
-    unsigned int* __restrict__ tile_count) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  GSplat s;
-  s.ix = 0; s.iy = 0; s.fx = 0.f; s.fy = 0.f;
-  s.l00 = 0.f; s.l10 = 0.f; s.l11 = 0.f; s.opacity = 0.f;
-  s.bx0 = 1; s.bx1 = 0; s.by0 = 1; s.by1 = 0;   // empty box = invisible
-  s.depth_bits = 0u; s.pad = 0u;
-
-  const double mx = means[3 * i + 0], my = means[3 * i + 1], mz = means[3 * i + 2];
-  double x, y, z;
-  {
-    // Camera point p = R mu + t summed left to right without fused multiply-adds,
-    // so the view depth (and its float32 sort key) is reproducible exactly.
-#pragma clang fp contract(off)
-    x = (double)cam.R[0] * mx + (double)cam.R[1] * my + (double)cam.R[2] * mz + (double)cam.t[0];
-    y = (double)cam.R[3] * mx + (double)cam.R[4] * my + (double)cam.R[5] * mz + (double)cam.t[1];
-    z = (double)cam.R[6] * mx + (double)cam.R[7] * my + (double)cam.R[8] * mz + (double)cam.t[2];
-  }
-  const double o = opacities[i];
-  const double lo = log(255.0 * o);
-  if (!(z > (double)cam.near_z) || !(lo >= 0.0)) { out[i] = s; return; }
-
-  // 3D covariance Sigma = R diag(exp(2 s)) R^T from the normalised quaternion
-  double qw = quats[4 * i + 0], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
-  const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  qw *= qn; qx *= qn; qy *= qn; qz *= qn;
-  const double Rq[3][3] = {
-      {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
-      {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
-      {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  const double s2[3] = {exp(2.0 * (double)log_scales[3 * i + 0]),
-                        exp(2.0 * (double)log_scales[3 * i + 1]),
-                        exp(2.0 * (double)log_scales[3 * i + 2])};
-  double S[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-      S[a][b] = Rq[a][0] * s2[0] * Rq[b][0] + Rq[a][1] * s2[1] * Rq[b][1] + Rq[a][2] * s2[2] * Rq[b][2];
-
-  // EWA Jacobian at the clamped camera point
-  const double fx = cam.fx, fy = cam.fy;
-  const double limx = 1.3 * ((double)cam.width / (2.0 * fx));
-  const double limy = 1.3 * ((double)cam.height / (2.0 * fy));
-  const double tx = fmin(limx, fmax(-limx, x / z)) * z;
-  const double ty = fmin(limy, fmax(-limy, y / z)) * z;
-  const double j00 = fx / z, j02 = -fx * tx / (z * z);
-  const double j11 = fy / z, j12 = -fy * ty / (z * z);
-  double T0[3], T1[3];   // T = J W, W the camera rotation
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    T0[b] = j00 * (double)cam.R[0 * 3 + b] + j02 * (double)cam.R[2 * 3 + b];
-    T1[b] = j11 * (double)cam.R[1 * 3 + b] + j12 * (double)cam.R[2 * 3 + b];
-  }
-  double U0[3], U1[3];   // T Sigma
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    U0[b] = T0[0] * S[0][b] + T0[1] * S[1][b] + T0[2] * S[2][b];
-    U1[b] = T1[0] * S[0][b] + T1[1] * S[1][b] + T1[2] * S[2][b];
-  }
-  const double sxx = U0[0] * T0[0] + U0[1] * T0[1] + U0[2] * T0[2] + 0.3;
-  const double sxy = U0[0] * T1[0] + U0[1] * T1[1] + U0[2] * T1[2];
-  const double syy = U1[0] * T1[0] + U1[1] * T1[1] + U1[2] * T1[2] + 0.3;
-  const double det = sxx * syy - sxy * sxy;
-  const double mux = fx * x / z + (double)cam.cx;
-  const double muy = fy * y / z + (double)cam.cy;
-  if (!(det > 0.0) || !(fabs(mux) < 1073741824.0) || !(fabs(muy) < 1073741824.0)) {
-    out[i] = s; return;
-  }
-  // conservative pixel box of {alpha >= 1/255}: |dx| <= sqrt(2 ln(255 o) Sxx)
-  const double r2 = 2.0 * lo;
-  const double hx = sqrt(r2 * sxx), hy = sqrt(r2 * syy);
-  double x0 = ceil(mux - hx - 0.5) - 1.0, x1 = floor(mux + hx - 0.5) + 1.0;
-  double y0 = ceil(muy - hy - 0.5) - 1.0, y1 = floor(muy + hy - 0.5) + 1.0;
-  x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
-  x1 = fmin(x1, (double)(cam.width - 1)); y1 = fmin(y1, (double)(cam.height - 1));
-  if (!(x0 <= x1) || !(y0 <= y1)) { out[i] = s; return; }
-
-  // scaled factor of the conic: q = (l00 dx + l10 dy)^2 + (l11 dy)^2 = log2(e)/2 d^T conic d
-  const double ks = 0.84932180028801904272;   // sqrt(log2(e) / 2)
-  const double l00 = sqrt(syy / det), l10 = -sxy / sqrt(det * syy), l11 = 1.0 / sqrt(syy);
-  const double flx = floor(mux), fly = floor(muy);
-  s.ix = (int)flx; s.iy = (int)fly;
-  s.fx = (float)(mux - flx); s.fy = (float)(muy - fly);
-  if (s.fx >= 1.0f) { s.fx = 0.0f; s.ix += 1; }
-  if (s.fy >= 1.0f) { s.fy = 0.0f; s.iy += 1; }
-  s.l00 = (float)(l00 * ks); s.l10 = (float)(l10 * ks); s.l11 = (float)(l11 * ks);
-  s.opacity = (float)o;
-  s.bx0 = (int16_t)x0; s.bx1 = (int16_t)x1; s.by0 = (int16_t)y0; s.by1 = (int16_t)y1;
-  s.depth_bits = __float_as_uint((float)z);
-  out[i] = s;
-  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
-  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_count[ty * tiles_x + tx], 1u);
-}
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the per-tile counts (one workgroup), capacity check
+// composite + per-(Gaussian, tile, region) reduction, one 16x16 tile per
+// workgroup; wave w owns the 8x8 quadrant (w&1, w>>1), lane l pixel (l&7, l>>3)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_scan(unsigned int* __restrict__ tile_count,
-                                                    unsigned int* __restrict__ tile_cursor,
-                                                    unsigned int* __restrict__ tile_start, int nt,
-                                                    unsigned long long capacity, Status* st) {
-  __shared__ unsigned long long part[1024];
-  const int tid = threadIdx.x;
-  const int per = (nt + 1023) / 1024;
-  const int b = tid * per, e = min(nt, b + per);
-  unsigned long long sum = 0;
-  for (int t = b; t < e; ++t) sum += tile_count[t];
-  part[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
-    unsigned long long v = tid >= o ? part[tid - o] : 0ull;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  unsigned long long run = part[tid] - sum;
-  const unsigned long long total = part[1023];
-  const bool over = total > capacity;
-  for (int t = b; t < e; ++t) {
-    const unsigned int c = tile_count[t];
-    tile_start[t] = over ? 0u : (unsigned int)run;
-    run += c;
-    tile_count[t] = 0u;       // ready for the next view
-    tile_cursor[t] = 0u;
-  }
-  if (tid == 0) {
-    tile_start[nt] = over ? 0u : (unsigned int)total;
-    st->total_pairs = over ? 0u : (unsigned int)total;
-    st->view_overflow = over ? 1u : 0u;
-    const unsigned int tot32 = total > 0xffffffffull ? 0xffffffffu : (unsigned int)total;
-    if (over) st->any_overflow = 1u;
-    if (tot32 > st->max_pairs) st->max_pairs = tot32;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// emit one (depth, id) key per (Gaussian, tile) into the tile's bucket
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n,
-                                              int tiles_x, int tile_shift,
-                                              const unsigned int* __restrict__ tile_start,
-                                              unsigned int* __restrict__ tile_cursor,
-                                              unsigned long long* __restrict__ keys, const Status* st) {
-  if (st->view_overflow) return;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const GSplat s = splats[i];
-  if (s.bx0 > s.bx1) return;
-  const unsigned long long key = ((unsigned long long)s.depth_bits << 32) | (unsigned long long)i;
-  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
-  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const int t = ty * tiles_x + tx;
-      const unsigned int pos = atomicAdd(&tile_cursor[t], 1u);
-      keys[tile_start[t] + pos] = key;
-    }
-}
-
-// Tiles whose list exceeds the LDS capacity are sorted in place in global
-// memory by one workgroup (rare; correctness path for dense tiles).
-__global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restrict__ keys,
-                                                   const unsigned int* __restrict__ tile_start,
-                                                   int sort_cap, const Status* st) {
-  if (st->view_overflow) return;
-  const int tile = blockIdx.x;
-  const unsigned int start = tile_start[tile];
-  const long long L = (long long)tile_start[tile + 1] - start;
-  if (L <= sort_cap) return;
-  unsigned long long* s = keys + start;
-  long long n2 = 1;
-  while (n2 < L) n2 <<= 1;
-  const int tid = threadIdx.x;
-  for (long long k = 2; k <= n2; k <<= 1) {
-    const long long hk = k >> 1;
-    for (long long i = tid; i < (n2 >> 1); i += 1024) {
-      const long long blk = i / hk, off = i - blk * hk;
-      const long long a = blk * k + off, b = blk * k + k - 1 - off;
-      if (b < L) cmp_swap(&s[a], &s[b]);
-    }
-    __syncthreads();
-    for (long long j = k >> 2; j >= 1; j >>= 1) {
-      for (long long i = tid; i < (n2 >> 1); i += 1024) {
-        const long long blk = i / j, off = i - blk * j;
-        const long long a = blk * 2 * j + off, b = a + j;
-        if (b < L) cmp_swap(&s[a], &s[b]);
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// composite + weighted sparse accumulate, one 16x16 tile per workgroup;
-// wave w owns the 8x8 quadrant (w&1, w>>1), lane l pixel (l&7, l>>3) of it.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_composite_acc(
+__global__ __launch_bounds__(256) void k_composite_rec(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
-    const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
-    const int* __restrict__ rmap, int n_regions, long long region_base,
-    const int* __restrict__ code_idx, const float* __restrict__ code_val, int k_code,
-    int m_atoms, float* __restrict__ acc, Status* st) {
+    const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
+    int H, const int* __restrict__ rmap, int n_regions, long long region_base,
+    const int* __restrict__ code_idx, const float* __restrict__ code_val, int k_code, int m_atoms,
+    float* __restrict__ acc, float2* __restrict__ rec, Status* st) {
   __shared__ unsigned long long s_keys[kSortCap];
   __shared__ GSplat s_g[kTileThreads];
   __shared__ unsigned int s_id[kTileThreads];
+  __shared__ float s_w[kTileThreads][2];
+  __shared__ int s_reg[kTileThreads];
+  __shared__ int s_first[2];
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -250,10 +57,27 @@ __global__ __launch_bounds__(256) void k_composite_acc(
     reg = rmap[(long long)py * W + px];
     if (reg < -1 || reg >= n_regions) { atomicOr(&st->data_error, 1u); reg = -1; }
   }
-  if (L == 0) return;   // region ids are validated on every pixel, empty tiles included
+  if (L == 0) return;   // (region ids are validated on every pixel, empty tiles included)
+  // the tile's record regions: r0 = region of the first pixel (thread order)
+  // with a region, r1 = first region different from r0
+  s_reg[tid] = reg;
+  if (tid < 2) s_first[tid] = kTileThreads;
+  __syncthreads();
+  if (reg >= 0) atomicMin(&s_first[0], tid);
+  __syncthreads();
+  const int r0 = s_first[0] < kTileThreads ? s_reg[s_first[0]] : -1;
+  if (reg >= 0 && reg != r0) atomicMin(&s_first[1], tid);
+  __syncthreads();
+  const int r1 = s_first[1] < kTileThreads ? s_reg[s_first[1]] : -1;
+  const int slot = reg < 0 ? 3 : reg == r0 ? 0 : reg == r1 ? 1 : 2;
+  const bool has0 = __ballot(slot == 0) != 0ull;
+  const bool has1 = __ballot(slot == 1) != 0ull;
+  const bool has2 = __ballot(slot == 2) != 0ull;
+  const float rg0 = __int_as_float(r0 >= 0 ? (int)(region_base + r0) : -1);
+  const float rg1 = __int_as_float(r1 >= 0 ? (int)(region_base + r1) : -1);
+
   const int qx0 = tile_x0 + qx, qx1 = qx0 + 7, qy0 = tile_y0 + qy, qy1 = qy0 + 7;
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
-
   const bool in_lds = L <= kSortCap;
   if (in_lds) {
     int n2 = 1;
@@ -267,7 +91,7 @@ __global__ __launch_bounds__(256) void k_composite_acc(
   bool done = !inside;
   unsigned long long count = 0;
   for (int b0 = 0; b0 < L; b0 += kTileThreads) {
-    if (__syncthreads_count(!done) == 0) break;
+    const bool all_done = __syncthreads_count(!done) == 0;
     const int j = b0 + tid;
     if (j < L) {
       const unsigned long long k = in_lds ? s_keys[j] : keys[start + j];
@@ -275,9 +99,11 @@ __global__ __launch_bounds__(256) void k_composite_acc(
       s_id[tid] = id;
       s_g[tid] = splats[id];
     }
+    s_w[tid][0] = 0.0f;
+    s_w[tid][1] = 0.0f;
     __syncthreads();
     const int nb = min(kTileThreads, L - b0);
-    if (__ballot(!done) != 0ull) {
+    if (!all_done && __ballot(!done) != 0ull) {
       for (int k = 0; k < nb; ++k) {
         const GSplat g = s_g[k];
         if (g.bx1 < qx0 || g.bx0 > qx1 || g.by1 < qy0 || g.by0 > qy1) continue;
@@ -301,45 +127,56 @@ __global__ __launch_bounds__(256) void k_composite_acc(
         const unsigned long long cm = __ballot(e > 0.0f);
         if (cm) {
           count += (unsigned long long)__popcll(cm);
-          unsigned long long rm = __ballot(e > 0.0f && reg >= 0);
-          const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
-          while (rm) {
-            const int l0 = __ffsll((long long)rm) - 1;
-            const int r0 = __shfl(reg, l0, 64);
-            const unsigned long long same = __ballot(reg == r0) & rm;
-            const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
-            const long long gr = (region_base + r0) * (long long)k_code;
-            for (int c = lane; c < k_code; c += 64) {
-              const int jj = code_idx[gr + c];
-              if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-              else if (jj >= 0) atomic_add_f32(&acc[row + (unsigned long long)jj], sum * code_val[gr + c]);
+          if (has0) {
+            const float sum = wave_sum(slot == 0 ? e : 0.0f);
+            if (lane == 0 && sum != 0.0f) atomicAdd(&s_w[k][0], sum);
+          }
+          if (has1) {
+            const float sum = wave_sum(slot == 1 ? e : 0.0f);
+            if (lane == 0 && sum != 0.0f) atomicAdd(&s_w[k][1], sum);
+          }
+          if (has2) {   // third and further regions of the tile: straight to the accumulator
+            unsigned long long rm = __ballot(e > 0.0f && slot == 2);
+            const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
+            while (rm) {
+              const int l0 = __ffsll((long long)rm) - 1;
+              const int rr = __builtin_amdgcn_readlane(reg, l0);
+              const unsigned long long same = __ballot(reg == rr) & rm;
+              const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
+              const long long gr = (region_base + rr) * (long long)k_code;
+              for (int c = lane; c < k_code; c += 64) {
+                const int jj = code_idx[gr + c];
+                if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+                else if (jj >= 0) atomic_add_f32(&acc[row + (unsigned long long)jj], sum * code_val[gr + c]);
+              }
+              rm &= ~same;
             }
-            rm &= ~same;
           }
         }
         if (__ballot(!done) == 0ull) break;
       }
     }
     __syncthreads();
+    if (j < L) {   // every pair's two record slots are written, zero weight included
+      const GSplat g = s_g[tid];
+      const int tx0 = g.bx0 >> 4, tx1 = g.bx1 >> 4, ty0 = g.by0 >> 4;
+      const unsigned int p = off[s_id[tid]] + (unsigned int)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+      rec[2ull * p] = make_float2(rg0, s_w[tid][0]);
+      rec[2ull * p + 1] = make_float2(rg1, s_w[tid][1]);
+    }
+    __syncthreads();
   }
-  if (lane == 0 && count) atomicAdd(&st->contrib, count);
+  if (lane == 0 && count) atomicAdd(&st->contrib, count);   // count is wave-uniform
 }
 
-// ---------------------------------------------------------------------------
-// Top-K per row (one wave per row), Eq. 6
-// ---------------------------------------------------------------------------
+// Eq. 6 on one row held by a wave (values in LDS or global memory).
 template <int NS>
-__global__ __launch_bounds__(256) void k_topk(const float* __restrict__ acc, long long n, int m, int k,
-                                              int* __restrict__ out_idx, float* __restrict__ out_val) {
-  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const float* a = acc + row * (long long)m;
+__device__ __forceinline__ void topk_row(const float* row, int m, int k, int lane, int* out_idx, float* out_val) {
   unsigned long long key[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int j = s * 64 + lane;
-    const float v = j < m ? a[j] : 0.0f;
+    const float v = j < m ? row[j] : 0.0f;
     key[s] = v > 0.0f ? (((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xffffffffu - (unsigned)j))
                       : 0ull;
   }
@@ -362,9 +199,66 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ acc, lon
     }
   }
   if (lane < k) {
-    out_idx[row * k + lane] = sel_i;
-    out_val[row * k + lane] = sel_i >= 0 ? sel_v / sum : 0.0f;
+    out_idx[lane] = sel_i;
+    out_val[lane] = sel_i >= 0 ? sel_v / sum : 0.0f;
   }
+}
+
+// ---------------------------------------------------------------------------
+// row build: G <= 64 consecutive Gaussians per workgroup, lane g of every wave
+// owns Gaussian i0 + g, wave w walks views w, w+4, ...; rows (stride M+1) in
+// LDS take the code of each record with LDS atomic adds; no barriers between
+// views.  Rows are written back coalesced, Top-K read from LDS.
+// ---------------------------------------------------------------------------
+template <int NS>
+__global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
+  extern __shared__ float rows[];            // G * (M+1)
+  const int M = a.m_atoms, stride = M + 1;
+  const long long i0 = (long long)blockIdx.x * G;
+  const int gn = (int)min((long long)G, a.n - i0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  float* acc = a.acc + i0 * M;
+  for (int j = tid; j < gn * M; j += 256) rows[(j / M) * stride + (j % M)] = acc[j];
+  __syncthreads();
+  const unsigned int cap = (unsigned int)a.capacity;
+  if (lane < gn) {
+    float* row = rows + lane * stride;
+    for (int v = wave; v < a.n_views; v += 4) {
+      const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0 + lane;
+      const unsigned int lo = min(offv[0], cap), hi = min(offv[1], cap);
+      const float2* recv = a.records + (long long)v * 2 * a.capacity;
+      for (unsigned int r = 2 * lo; r < 2 * hi; ++r) {
+        const float2 rc = recv[r];
+        const int reg = __float_as_int(rc.x);
+        if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
+        const long long gr = (long long)reg * a.k_code;
+        for (int c = 0; c < a.k_code; ++c) {
+          const int jj = a.code_idx[gr + c];
+          if (jj >= M) atomicOr(&a.status->data_error, 2u);
+          else if (jj >= 0) atomicAdd(&row[jj], rc.y * a.code_val[gr + c]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < gn * M; j += 256) acc[j] = rows[(j / M) * stride + (j % M)];
+  if (a.k_top > 0) {
+    for (int g = wave; g < gn; g += 4)
+      topk_row<NS>(rows + g * stride, M, a.k_top, lane, a.topk_idx + (i0 + g) * a.k_top,
+                   a.topk_val + (i0 + g) * a.k_top);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Top-K per row of an accumulator in memory (one wave per row), Eq. 6
+// ---------------------------------------------------------------------------
+template <int NS>
+__global__ __launch_bounds__(256) void k_topk(const float* __restrict__ acc, long long n, int m, int k,
+                                              int* __restrict__ out_idx, float* __restrict__ out_val) {
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  topk_row<NS>(acc + row * (long long)m, m, k, lane, out_idx + row * k, out_val + row * k);
 }
 
 __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += st->contrib; }
@@ -372,40 +266,35 @@ __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += s
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_bin_view(const BinArgs& a, hipStream_t s) {
-  const int nb = (int)((a.n + 255) / 256);
-  if (a.n > 0) {
-    StageTimer::begin(kStProject, s);
-    hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, s, a.means, a.log_scales, a.quats,
-                       a.opacities, a.n, a.cam, a.tiles_x, a.tile_shift, a.splats, a.tile_count);
-    StageTimer::end(kStProject, s);
-  }
-  StageTimer::begin(kStScan, s);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, a.tile_count, a.tile_cursor,
-                     a.tile_start, a.n_tiles, (unsigned long long)a.capacity, a.status);
-  StageTimer::end(kStScan, s);
-  if (a.n > 0) {
-    StageTimer::begin(kStEmit, s);
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_shift,
-                       a.tile_start, a.tile_cursor, a.keys, a.status);
-    StageTimer::end(kStEmit, s);
-  }
-  StageTimer::begin(kStSortBig, s);
-  hipLaunchKernelGGL(k_sort_big, dim3(a.n_tiles), dim3(1024), 0, s, a.keys, a.tile_start, a.sort_cap,
-                     a.status);
-  StageTimer::end(kStSortBig, s);
-  return hipGetLastError();
-}
-
-hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s) {
+hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   hipError_t e = launch_bin_view(a.bin, s);
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_acc, dim3(b.n_tiles), dim3(kTileThreads), 0, s, b.splats,
-                     b.tile_start, b.keys, b.tiles_x, b.cam.width, b.cam.height, a.rmap, a.n_regions,
-                     a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, b.status);
+  hipLaunchKernelGGL(k_composite_rec, dim3(b.n_tiles), dim3(kTileThreads), 0, s, b.splats, b.tile_start,
+                     b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.rmap, a.n_regions,
+                     a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, a.records, b.status);
   StageTimer::end(kStComposite, s);
+  return hipGetLastError();
+}
+
+int rowbuild_group(int m) { return std::max(1, std::min(64, 16384 / (m + 1))); }
+
+hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int G = rowbuild_group(a.m_atoms);
+  const int grid = (int)((a.n + G - 1) / G);
+  const size_t lds = sizeof(float) * (size_t)G * (a.m_atoms + 1);
+  const int ns = (a.m_atoms + 63) / 64;
+  StageTimer::begin(kStRowBuild, s);
+  if (ns <= 1) hipLaunchKernelGGL(k_rowbuild<1>, dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 2) hipLaunchKernelGGL(k_rowbuild<2>, dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 4) hipLaunchKernelGGL(k_rowbuild<4>, dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 8) hipLaunchKernelGGL(k_rowbuild<8>, dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 16) hipLaunchKernelGGL(k_rowbuild<16>, dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 32) hipLaunchKernelGGL(k_rowbuild<32>, dim3(grid), dim3(256), lds, s, a, G);
+  else hipLaunchKernelGGL(k_rowbuild<64>, dim3(grid), dim3(256), lds, s, a, G);
+  StageTimer::end(kStRowBuild, s);
   return hipGetLastError();
 }
 

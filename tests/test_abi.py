@@ -60,22 +60,26 @@ def test_uplift_argument_validation():
     lib = L.load()
     v, keep = _views()
     g = L.Gaussians(10, 1, 1, 1, 1)
-    ws = lib.scoup_uplift_workspace_bytes(10, C.byref(v), 0)
+    ws = lib.scoup_uplift_workspace_bytes(10, C.byref(v), 0, 0)
     assert ws > 0
-    assert lib.scoup_uplift_workspace_bytes(10, C.byref(v), 1 << 20) >= (1 << 20) * 8
-    # NULL acc / workspace, misaligned workspace, bad K, mismatched map size
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), None, 0, 256, ws, None, None) == L.E_ARG
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, None, ws, None, None) == L.E_ARG
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, 257, ws, None, None) == L.E_ARG
-    assert lib.scoup_uplift(C.byref(g), C.byref(v), 0, 256, 256, 256, 256, ws, None, None) == L.E_ARG
-    assert lib.scoup_uplift(C.byref(g), C.byref(v), 65, 256, 256, 256, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_workspace_bytes(10, C.byref(v), 1 << 20, 1) >= (1 << 20) * 40
+    cap = 1 << 16
+    ws = lib.scoup_uplift_workspace_bytes(10, C.byref(v), cap, 1)
+    # NULL acc / workspace, misaligned workspace, bad K, bad capacity, mismatched map size
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), None, 0, cap, 1, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, cap, 1, None, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, cap, 1, 257, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, 0, 1, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift(C.byref(g), C.byref(v), 0, 256, 256, 256, cap, 1, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift(C.byref(g), C.byref(v), 65, 256, 256, 256, cap, 1, 256, ws, None, None) == L.E_ARG
     bad, keep2 = _views(offsets=[0, 100])
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(bad), 256, 0, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(bad), 256, 0, cap, 1, 256, ws, None, None) == L.E_ARG
     assert b"map_offsets" in lib.scoup_last_error()
-    # workspace smaller than the fixed part
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, 256, 1024, None, None) == L.E_WORKSPACE
+    # workspace smaller than the capacity and view batch need
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(v), 256, 0, cap, 1, 256, 1024, None, None) \
+        == L.E_WORKSPACE
     assert lib.scoup_required_pair_capacity() > 0
     neg = L.Gaussians(-1, 1, 1, 1, 1)
-    assert lib.scoup_uplift_accumulate(C.byref(neg), C.byref(v), 256, 0, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(neg), C.byref(v), 256, 0, cap, 1, 256, ws, None, None) == L.E_ARG
     big, keep3 = _views(width=40000)
-    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(big), 256, 0, 256, ws, None, None) == L.E_ARG
+    assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(big), 256, 0, cap, 1, 256, ws, None, None) == L.E_ARG

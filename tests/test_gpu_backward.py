@@ -1,8 +1,11 @@
 """GPU backward of render + decode against the FP64 oracle's gradient.
 
-Tolerance (written here): |g_gpu - g_ref| <= 1e-4 max(|g_ref|, 1e-3 ||g_ref||_inf)
-per entry, for dL/dw_hat (N, K) and dL/dC (M, D).  The oracle itself is pinned
-against FP64 central finite differences in tests/test_oracle_pins.py.
+Tolerance (written here), per entry of dL/dw_hat (N, K) and dL/dC (M, D):
+    |g_gpu - g_ref| <= 1e-4 |g_ref| + 1e-5 a_ref
+where a_ref is the same sum taken over absolute values of its terms (float32
+summation error grows with the magnitude of the terms, not with a result that
+cancels).  The oracle itself is pinned against FP64 central finite differences
+in tests/test_oracle_pins.py.
 """
 import numpy as np
 import pytest
@@ -19,12 +22,14 @@ pytestmark = pytest.mark.gpu
 REL = 1e-4
 
 
-def _check_grad(got, ref, name):
+def _check_grad(got, ref, absref, name):
     got = np.asarray(got, np.float64); ref = np.asarray(ref, np.float64)
+    err = np.abs(got - ref)
+    tol = REL * np.abs(ref) + 1e-5 * absref
     scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
-    err = np.abs(got - ref) / scale
-    print(f"[{name}] max rel err {err.max():.3g} (|ref|max {np.abs(ref).max():.3g})")
-    assert err.max() <= REL, (name, float(err.max()))
+    print(f"[{name}] max err/tol {float((err / np.maximum(tol, 1e-300)).max()):.3g}, max rel err "
+          f"{float((err / scale).max()):.3g} (|ref|max {np.abs(ref).max():.3g})")
+    assert (err <= tol).all(), (name, float((err / np.maximum(tol, 1e-300)).max()))
 
 
 def _loss_torch(F, tf, targets, sum_loss=False):
@@ -66,12 +71,17 @@ def test_backward_matches_oracle_full():
     Lref = sum(OB.cosine_loss(F, t, c, ncov) for F, t, c in zip(Fr, targets, covs))
     assert float(loss) == pytest.approx(Lref, rel=1e-5)
     gC = np.zeros((m, d)); gw = np.zeros((n, k))
+    aC = np.zeros((m, d)); aw = np.zeros((n, k))
+    Cabs = np.abs(C.astype(np.float64))
     for rr, F, t, c in zip(rrs, Fr, targets, covs):
         G = OB.cosine_loss_grad(F, t, c, ncov)
+        rows = np.arange(rr.coeff.shape[0])
         gC += OB.codebook_grad(rr.coeff, G)
-        OB.coeff_grad(rr.weights, np.arange(rr.coeff.shape[0]), ti, G @ C.astype(np.float64).T, gw)
-    _check_grad(dC.grad.cpu().numpy(), gC, "dL/dC")
-    _check_grad(dtv.grad.cpu().numpy(), gw, "dL/dw_hat")
+        aC += OB.codebook_grad(np.abs(rr.coeff), np.abs(G))
+        OB.coeff_grad(rr.weights, rows, ti, G @ C.astype(np.float64).T, gw)
+        OB.coeff_grad(rr.weights, rows, ti, np.abs(G) @ Cabs.T, aw)
+    _check_grad(dC.grad.cpu().numpy(), gC, aC, "dL/dC")
+    _check_grad(dtv.grad.cpu().numpy(), gw, aw, "dL/dw_hat")
 
 
 def test_backward_workload_size_sampled_gaussians():
@@ -104,6 +114,7 @@ def test_backward_workload_size_sampled_gaussians():
     rows = rng.choice(cand, 500, replace=False)
     from oracle import project as OP
     gw = np.zeros((500, k))
+    aw = np.zeros((500, k))
     row_of = -np.ones(n, np.int64); row_of[rows] = np.arange(500)
     for cam, t in zip(cams, targets):
         proj = OP.project(g, cam)
@@ -123,4 +134,5 @@ def test_backward_workload_size_sampled_gaussians():
         sel = row_of[w.gauss] >= 0
         sub = type(w)(row_of[w.gauss[sel]], w.pixel[sel], w.e[sel], w.t_final, {})
         OB.coeff_grad(sub, prow, ti[rows], dW, gw)
-    _check_grad(gw_gpu[rows], gw, "dL/dw_hat (500 sampled Gaussians, 8 views 512x384)")
+        OB.coeff_grad(sub, prow, ti[rows], np.abs(G) @ np.abs(C.astype(np.float64)).T, aw)
+    _check_grad(gw_gpu[rows], gw, aw, "dL/dw_hat (500 sampled Gaussians, 8 views 512x384)")

@@ -54,7 +54,10 @@ def test_render_fp32_matches_oracle(res, m, k):
         err = np.abs(got - rr.coeff).sum(1)
         ref = np.abs(rr.coeff).sum(1)
         assert (err <= 1e-5 * ref + amb + 1e-9).all(), float((err - 1e-5 * ref - amb).max())
-        assert np.allclose(tf.cpu().numpy().reshape(-1), rr.t_final, rtol=2e-5, atol=1e-7)
+        # final transmittance; a marginal decision (see the oracle) may change it
+        ok = np.ones(rr.t_final.shape[0], bool)
+        ok[list(rr.weights.marginal.keys())] = False
+        assert np.allclose(tf.cpu().numpy().reshape(-1)[ok], rr.t_final[ok], rtol=2e-5, atol=1e-7)
         slack = sum(s for *_, s in OC.ambiguity(rr.weights.marginal))
         assert abs(nc - rr.weights.n_contrib) <= slack
         print(f"[render {res} M={m}] contrib={nc} max L1 rel err={float((err / np.maximum(ref, 1e-30)).max()):.3g}")

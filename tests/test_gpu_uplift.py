@@ -88,16 +88,29 @@ def test_resume_accumulate_equals_full():
     assert np.allclose(f, r, rtol=1e-5, atol=1e-12)
 
 
-def test_workspace_retry_path():
-    """A pair capacity far too small is reported and the wrapper's retry succeeds."""
+def test_workspace_retry_path_and_view_batches():
+    """A pair capacity far too small is reported and the wrapper's retry succeeds;
+    summing records one view at a time equals one pass over all views."""
     require_gpu()
     sc = sg.make_scene("tiny")
     dg, dv = to_device(sc.gaussians, sc.views)
     ws = P.api.Workspace()
+    from paper_2605_13600_amd import _lib as L
+    import ctypes as C
+    lib = L.load()
+    gs, vs = dg.struct(), dv.struct()
+    nb = lib.scoup_uplift_workspace_bytes(dg.n, C.byref(vs), 16, 1)
+    buf = ws.get(nb)
+    acc0 = torch.zeros((dg.n, 64), dtype=torch.float32, device="cuda")
+    st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), acc0.data_ptr(), 0, 16, 1, buf.data_ptr(),
+                                     buf.numel(), None, None)
+    assert st == L.E_WORKSPACE and lib.scoup_required_pair_capacity() > 16
     P.api._capacity_cache.clear()
-    acc, nc = P.uplift_accumulate(dg, dv, workspace=ws, pair_capacity=1)
     ref = OU.uplift_accumulate(sc.gaussians, sc.views)
-    PT.check_acc(acc.cpu().numpy(), ref.acc, ref.amb)
+    for vb in (1, 3, 0):
+        acc, nc = P.uplift_accumulate(dg, dv, workspace=ws, pair_capacity=1, view_batch=vb)
+        PT.check_acc(acc.cpu().numpy(), ref.acc, ref.amb)
+        assert abs(nc - ref.n_contrib) <= ref.count_slack
 
 
 def test_empty_and_invisible():
