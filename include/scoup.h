@@ -96,8 +96,8 @@ typedef struct {
 } scoup_views;
 
 /* Workspace bytes for scoup_uplift / scoup_uplift_accumulate.
- *   pair_capacity  capacity for (Gaussian, 16x16-tile) pairs of one view
- *                  (0 picks 4 pairs per Gaussian)
+ *   pair_capacity  capacity for (Gaussian, 8x8-block) pairs of one view
+ *                  (0 picks 6 pairs per Gaussian)
  *   view_batch     views whose per-pair records are kept before they are summed
  *                  into the accumulator (0 = all views: one pass over acc)
  * The workspace holds, per view of a batch, (n+1) pair offsets and two 8-byte

@@ -151,7 +151,7 @@ def _uplift_call(g: DeviceGaussians, views: DeviceViews, acc: torch.Tensor, accu
     ws = workspace or _workspace(dev)
     gs, vs = g.struct(), views.struct()
     key = ("uplift", g.n, views.n_views, int(views._moff[-1]))
-    cap = max(int(pair_capacity), _capacity_cache.get(key, 0), 4 * g.n, 1 << 16)
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0), 6 * g.n, 1 << 16)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     for _ in range(4):
         vb = int(view_batch) if view_batch else max(1, views.n_views)

@@ -73,9 +73,9 @@ int64_t capacity_for(int64_t n, int max_tiles, size_t bytes) {
   return std::min<int64_t>(std::max<int64_t>(cap, 0), 0x7fffffffLL);
 }
 
-int max_tiles_of(const scoup_views* v) {
+int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
   int mt = 1;
-  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height));
+  for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height, 3));
   return mt;
 }
 
@@ -238,7 +238,7 @@ size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* view
                                     int32_t view_batch) {
   if (!views || n_gaussians < 0) return 0;
   if (views->n_views > 0 && !views->cams) return 0;
-  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(4 * n_gaussians, 1 << 16);
+  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(6 * n_gaussians, 1 << 16);
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : views->n_views, views->n_views));
   return bin_layout(n_gaussians, max_tiles_of(views), pair_capacity, vb, vb).total;
 }
@@ -275,7 +275,7 @@ scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* 
 
   UpliftViewArgs a{};
   BinArgs& b = a.bin;
-  fill_bin(b, g, base, L, pair_capacity, 4, kSortCap);
+  fill_bin(b, g, base, L, pair_capacity, 3, 2048);
   a.code_idx = v->code_idx; a.code_val = v->code_val;
   a.k_code = v->k_code; a.m_atoms = v->m_atoms;
   a.acc = acc;
@@ -295,8 +295,8 @@ scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* 
         const int i = v0 + j;
         const scoup_camera& c = v->cams[i];
         b.cam = to_dev(c);
-        b.tiles_x = (c.width + kTile - 1) / kTile;
-        b.n_tiles = tiles_of(c.width, c.height);
+        b.tiles_x = (c.width + 7) / 8;
+        b.n_tiles = tiles_of(c.width, c.height, 3);
         b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
         a.records = rec_all + (size_t)j * 2 * (size_t)pair_capacity;
         a.rmap = v->region_maps + v->map_offsets[i];

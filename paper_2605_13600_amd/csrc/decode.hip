@@ -28,6 +28,28 @@ template <> struct Mfma<SCOUP_F32> { static constexpr int KS = 2, FB = 4, ES = 4
 template <> struct Mfma<SCOUP_BF16> { static constexpr int KS = 16, FB = 16, ES = 2; };
 template <> struct Mfma<SCOUP_FP8_E4M3> { static constexpr int KS = 64, FB = 32, ES = 1; };
 
+// operand fragment of one lane and the matching MFMA
+template <int T> struct Frag;
+template <> struct Frag<SCOUP_F32> {
+  typedef float type;
+  static __device__ __forceinline__ f16v mfma(float a, float b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Frag<SCOUP_BF16> {
+  typedef bf16x8 type;
+  static __device__ __forceinline__ f16v mfma(bf16x8 a, bf16x8 b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Frag<SCOUP_FP8_E4M3> {
+  typedef i32x8 type;
+  // format 0 = FP8 E4M3 for both operands; E8M0 block scales 127 = 2^0
+  static __device__ __forceinline__ f16v mfma(i32x8 a, i32x8 b, f16v c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  }
+};
+
 constexpr int kDecBM = 128;
 constexpr int kDecThreads = 512;
 
@@ -90,6 +112,15 @@ __global__ void k_fp8_scale(const unsigned int* __restrict__ maxbits, float* sca
 
 __device__ __forceinline__ void store_f(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_f(uint16_t* p, float v) { *p = f32_to_bf16_rne(v); }
+// four consecutive outputs (16-byte aligned float32 / 8-byte aligned bfloat16)
+__device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void store4(uint16_t* p, float a, float b, float c, float d) {
+  const unsigned int lo = (unsigned int)f32_to_bf16_rne(a) | ((unsigned int)f32_to_bf16_rne(b) << 16);
+  const unsigned int hi = (unsigned int)f32_to_bf16_rne(c) | ((unsigned int)f32_to_bf16_rne(d) << 16);
+  *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
+}
 
 template <int T, int NCT, typename TOut>
 __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restrict__ A, long long P, int M,
@@ -130,54 +161,61 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
       *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
     }
     __syncthreads();
+    // codebook fragments for k-step ks are loaded one step ahead of their MFMAs
+    typename Frag<T>::type bcur[NCT], bnext[NCT];
+    const typename Frag<T>::type* Bf = reinterpret_cast<const typename Frag<T>::type*>(Bp);
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) bcur[c] = Bf[((long long)(ct0 + c) * nks + k0 / F::KS) * 64 + lane];
     for (int kk = 0; kk < kcur; kk += F::KS) {
       const int ks = (k0 + kk) / F::KS;
-      const int kb = (kk + (lane >> 5) * (F::KS / 2)) * F::ES;   // byte offset in the LDS row
-      if constexpr (T == SCOUP_F32) {
-        const float a0 = *reinterpret_cast<const float*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
-        const float a1 = *reinterpret_cast<const float*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+      if (kk + F::KS < kcur) {
 #pragma unroll
-        for (int c = 0; c < NCT; ++c) {
-          const float b = reinterpret_cast<const float*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
-          acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b, acc[0][c], 0, 0, 0);
-          acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b, acc[1][c], 0, 0, 0);
-        }
-      } else if constexpr (T == SCOUP_BF16) {
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
-#pragma unroll
-        for (int c = 0; c < NCT; ++c) {
-          const bf16x8 b = reinterpret_cast<const bf16x8*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
-          acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][c], 0, 0, 0);
-          acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][c], 0, 0, 0);
-        }
-      } else {
-        const i32x8 a0 = *reinterpret_cast<const i32x8*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
-        const i32x8 a1 = *reinterpret_cast<const i32x8*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
-#pragma unroll
-        for (int c = 0; c < NCT; ++c) {
-          const i32x8 b = reinterpret_cast<const i32x8*>(Bp)[((long long)(ct0 + c) * nks + ks) * 64 + lane];
-          // format 0 = FP8 E4M3 for both operands; E8M0 block scales 127 = 2^0
-          acc[0][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a0, b, acc[0][c], 0, 0, 0, 127, 0, 127);
-          acc[1][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a1, b, acc[1][c], 0, 0, 0, 127, 0, 127);
-        }
+        for (int c = 0; c < NCT; ++c) bnext[c] = Bf[((long long)(ct0 + c) * nks + ks + 1) * 64 + lane];
       }
+      const int kb = (kk + (lane >> 5) * (F::KS / 2)) * F::ES;   // byte offset in the LDS row
+      const typename Frag<T>::type a0 =
+          *reinterpret_cast<const typename Frag<T>::type*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
+      const typename Frag<T>::type a1 =
+          *reinterpret_cast<const typename Frag<T>::type*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+      // operands swapped: the tile is F^T = C^T W^T, so each lane owns one pixel
+      // and runs of four consecutive feature columns (vector stores below)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        acc[0][c] = Frag<T>::mfma(bcur[c], a0, acc[0][c]);
+        acc[1][c] = Frag<T>::mfma(bcur[c], a1, acc[1][c]);
+      }
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) bcur[c] = bnext[c];
     }
     __syncthreads();
   }
   float mul = out_mul;
   if (cb_scale) mul /= *cb_scale;
-  // D element (row 8(r/4) + 4(l/32) + r%4, col l%32) of each 32x32 tile
+  // element (row 8(r/4) + 4(l/32) + r%4, col l%32) of each 32x32 tile of F^T:
+  // pixel p0 + rh*64 + a*32 + l%32, feature column (ct0+c)*32 + 8(r/4) + 4(l/32) + r%4
+  const bool vec = (ldo & 3) == 0;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a) {
+    const long long p = p0 + rh * 64 + a * 32 + (lane & 31);
+    if (p >= P) continue;
+    TOut* orow = out + p * ldo;
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const long long p = p0 + rh * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = (ct0 + c) * 32 + (lane & 31);
-        if (p < P && col < n_valid) store_f(out + p * ldo + col, acc[a][c][r] * mul);
+      for (int rg = 0; rg < 4; ++rg) {
+        const int d0 = (ct0 + c) * 32 + 8 * rg + 4 * (lane >> 5);
+        const float v0 = acc[a][c][4 * rg] * mul, v1 = acc[a][c][4 * rg + 1] * mul;
+        const float v2 = acc[a][c][4 * rg + 2] * mul, v3 = acc[a][c][4 * rg + 3] * mul;
+        if (vec && d0 + 3 < n_valid) {
+          store4(orow + d0, v0, v1, v2, v3);
+        } else {
+          if (d0 < n_valid) store_f(orow + d0, v0);
+          if (d0 + 1 < n_valid) store_f(orow + d0 + 1, v1);
+          if (d0 + 2 < n_valid) store_f(orow + d0 + 2, v2);
+          if (d0 + 3 < n_valid) store_f(orow + d0 + 3, v3);
+        }
       }
+  }
 }
 
 int decode_npad(int d) {

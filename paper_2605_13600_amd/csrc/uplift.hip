@@ -3,12 +3,12 @@
 // gfx950 (CDNA4), wave64.
 //
 // Paper mapping:
-//   k_composite_rec  Eq. 2 weights e = alpha T on one 16x16 tile, reduced per
-//                    (Gaussian, tile region) -- the pixels of a region share one
+//   k_composite_blk  Eq. 2 weights e = alpha T on one 8x8 block, reduced per
+//                    (Gaussian, block region) -- the pixels of a region share one
 //                    code (Sec. 4.1), so Algorithm 1's inner loop collapses to
 //                    one weight per (Gaussian, region) touch.  The first two
-//                    regions of a tile go to fixed record slots of the
-//                    (Gaussian, tile) pair; further regions are added to the
+//                    regions of a block go to fixed record slots of the
+//                    (Gaussian, block) pair; further regions are added to the
 //                    accumulator with atomics.
 //   k_rowbuild       Eq. 5 / Algorithm 1: w_i[j] += c_j * weight for every
 //                    record of Gaussian i over a batch of views, in LDS; rows
@@ -26,30 +26,35 @@ namespace scoup {
 
 
 // ---------------------------------------------------------------------------
-// composite + per-(Gaussian, tile, region) reduction, one 16x16 tile per
-// workgroup; wave w owns the 8x8 quadrant (w&1, w>>1), lane l pixel (l&7, l>>3)
+// composite + per-(Gaussian, block, region) reduction: one 8x8 pixel block per
+// workgroup (one wave), lane l = pixel (l & 7, l >> 3) of the block.
+// Per batch of 64 depth-sorted Gaussians the wave writes every lane's weight
+// e into an LDS matrix E[Gaussian][pixel]; afterwards lane k sums row k over
+// the pixels of the block's two record regions (a transposed reduction: no
+// cross-lane traffic inside the sequential compositing loop) and writes the
+// pair's two records.  Pixels of a third or further region in the block
+// (rare) are reduced across the wave and added to the accumulator directly.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_composite_rec(
+constexpr int kBlkSortCap = 2048;
+constexpr int kEStride = 65;
+
+__global__ __launch_bounds__(64) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
-    const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
+    unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, const int* __restrict__ rmap, int n_regions, long long region_base,
     const int* __restrict__ code_idx, const float* __restrict__ code_val, int k_code, int m_atoms,
     float* __restrict__ acc, float2* __restrict__ rec, Status* st) {
-  __shared__ unsigned long long s_keys[kSortCap];
-  __shared__ GSplat s_g[kTileThreads];
-  __shared__ unsigned int s_id[kTileThreads];
-  __shared__ float s_w[kTileThreads][2];
-  __shared__ int s_reg[kTileThreads];
-  __shared__ int s_first[2];
+  __shared__ float smem[64 * kEStride];       // sort keys (2048 x 8 B) first, then E
+  __shared__ GSplat s_g[64];
+  __shared__ unsigned int s_id[64];
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int qx = (wave & 1) * 8, qy = (wave >> 1) * 8;
-  const int lx = qx + (lane & 7), ly = qy + (lane >> 3);
-  const int tile_x0 = tx * kTile, tile_y0 = ty * kTile;
+  const int lane = threadIdx.x;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int tile_x0 = tx * 8, tile_y0 = ty * 8;
   const int px = tile_x0 + lx, py = tile_y0 + ly;
   const bool inside = px < W && py < H;
   int reg = -1;
@@ -57,56 +62,47 @@ __global__ __launch_bounds__(256) void k_composite_rec(
     reg = rmap[(long long)py * W + px];
     if (reg < -1 || reg >= n_regions) { atomicOr(&st->data_error, 1u); reg = -1; }
   }
-  if (L == 0) return;   // (region ids are validated on every pixel, empty tiles included)
-  // the tile's record regions: r0 = region of the first pixel (thread order)
-  // with a region, r1 = first region different from r0
-  s_reg[tid] = reg;
-  if (tid < 2) s_first[tid] = kTileThreads;
-  __syncthreads();
-  if (reg >= 0) atomicMin(&s_first[0], tid);
-  __syncthreads();
-  const int r0 = s_first[0] < kTileThreads ? s_reg[s_first[0]] : -1;
-  if (reg >= 0 && reg != r0) atomicMin(&s_first[1], tid);
-  __syncthreads();
-  const int r1 = s_first[1] < kTileThreads ? s_reg[s_first[1]] : -1;
+  if (L == 0) return;   // (region ids are validated on every pixel, empty blocks included)
+  // record regions: r0 = region of the first pixel with one, r1 = first other region
+  const unsigned long long any = __ballot(reg >= 0);
+  const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
+  const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
+  const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
   const int slot = reg < 0 ? 3 : reg == r0 ? 0 : reg == r1 ? 1 : 2;
-  const bool has0 = __ballot(slot == 0) != 0ull;
-  const bool has1 = __ballot(slot == 1) != 0ull;
+  const unsigned long long mask0 = __ballot(slot == 0), mask1 = __ballot(slot == 1);
   const bool has2 = __ballot(slot == 2) != 0ull;
   const float rg0 = __int_as_float(r0 >= 0 ? (int)(region_base + r0) : -1);
   const float rg1 = __int_as_float(r1 >= 0 ? (int)(region_base + r1) : -1);
 
-  const int qx0 = tile_x0 + qx, qx1 = qx0 + 7, qy0 = tile_y0 + qy, qy1 = qy0 + 7;
-  const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
-  const bool in_lds = L <= kSortCap;
-  if (in_lds) {
+  if (L <= kBlkSortCap) {        // depth order in LDS, written back for the batches
+    unsigned long long* sk = reinterpret_cast<unsigned long long*>(smem);
     int n2 = 1;
     while (n2 < L) n2 <<= 1;
-    for (int j = tid; j < n2; j += kTileThreads) s_keys[j] = j < L ? keys[start + j] : ~0ull;
+    for (int j = lane; j < n2; j += 64) sk[j] = j < L ? keys[start + j] : ~0ull;
     __syncthreads();
-    bitonic_lds(s_keys, n2, tid, kTileThreads);
+    bitonic_lds(sk, n2, lane, 64);
+    for (int j = lane; j < L; j += 64) keys[start + j] = sk[j];
+    __syncthreads();
   }
-
+  float* E = smem;
+  const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = 1.0f;
   bool done = !inside;
   unsigned long long count = 0;
-  for (int b0 = 0; b0 < L; b0 += kTileThreads) {
-    const bool all_done = __syncthreads_count(!done) == 0;
-    const int j = b0 + tid;
+  for (int b0 = 0; b0 < L; b0 += 64) {
+    const bool all_done = __ballot(!done) == 0ull;
+    const int j = b0 + lane;
+    const int nb = min(64, L - b0);
     if (j < L) {
-      const unsigned long long k = in_lds ? s_keys[j] : keys[start + j];
-      const unsigned int id = (unsigned int)k;
-      s_id[tid] = id;
-      s_g[tid] = splats[id];
+      const unsigned int id = (unsigned int)keys[start + j];
+      s_id[lane] = id;
+      s_g[lane] = splats[id];
     }
-    s_w[tid][0] = 0.0f;
-    s_w[tid][1] = 0.0f;
     __syncthreads();
-    const int nb = min(kTileThreads, L - b0);
-    if (!all_done && __ballot(!done) != 0ull) {
+    unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
+    if (!all_done) {
       for (int k = 0; k < nb; ++k) {
         const GSplat g = s_g[k];
-        if (g.bx1 < qx0 || g.bx0 > qx1 || g.by1 < qy0 || g.by0 > qy1) continue;
         const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
         const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
         const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
@@ -126,16 +122,10 @@ __global__ __launch_bounds__(256) void k_composite_rec(
         }
         const unsigned long long cm = __ballot(e > 0.0f);
         if (cm) {
+          contributed |= 1ull << k;
           count += (unsigned long long)__popcll(cm);
-          if (has0) {
-            const float sum = wave_sum(slot == 0 ? e : 0.0f);
-            if (lane == 0 && sum != 0.0f) atomicAdd(&s_w[k][0], sum);
-          }
-          if (has1) {
-            const float sum = wave_sum(slot == 1 ? e : 0.0f);
-            if (lane == 0 && sum != 0.0f) atomicAdd(&s_w[k][1], sum);
-          }
-          if (has2) {   // third and further regions of the tile: straight to the accumulator
+          E[k * kEStride + lane] = e;
+          if (has2) {   // third and further regions of the block: straight to the accumulator
             unsigned long long rm = __ballot(e > 0.0f && slot == 2);
             const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
             while (rm) {
@@ -157,12 +147,22 @@ __global__ __launch_bounds__(256) void k_composite_rec(
       }
     }
     __syncthreads();
-    if (j < L) {   // every pair's two record slots are written, zero weight included
-      const GSplat g = s_g[tid];
-      const int tx0 = g.bx0 >> 4, tx1 = g.bx1 >> 4, ty0 = g.by0 >> 4;
-      const unsigned int p = off[s_id[tid]] + (unsigned int)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
-      rec[2ull * p] = make_float2(rg0, s_w[tid][0]);
-      rec[2ull * p + 1] = make_float2(rg1, s_w[tid][1]);
+    if (lane < nb) {   // every pair's two record slots are written, zero weight included
+      float w0 = 0.0f, w1 = 0.0f;
+      if ((contributed >> lane) & 1ull) {
+        const float* row = E + lane * kEStride;
+#pragma unroll 8
+        for (int p = 0; p < 64; ++p) {
+          const float x = row[p];
+          if ((mask0 >> p) & 1ull) w0 += x;
+          else if ((mask1 >> p) & 1ull) w1 += x;
+        }
+      }
+      const GSplat g = s_g[lane];
+      const int bx0 = g.bx0 >> 3, bx1 = g.bx1 >> 3, by0 = g.by0 >> 3;
+      const unsigned int p = off[s_id[lane]] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+      rec[2ull * p] = make_float2(rg0, w0);
+      rec[2ull * p + 1] = make_float2(rg1, w1);
     }
     __syncthreads();
   }
@@ -232,10 +232,19 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
         const int reg = __float_as_int(rc.x);
         if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
         const long long gr = (long long)reg * a.k_code;
-        for (int c = 0; c < a.k_code; ++c) {
-          const int jj = a.code_idx[gr + c];
-          if (jj >= M) atomicOr(&a.status->data_error, 2u);
-          else if (jj >= 0) atomicAdd(&row[jj], rc.y * a.code_val[gr + c]);
+        for (int c = 0; c < a.k_code; c += 4) {     // issue four slots' loads before their adds
+          int jj[4];
+          float cv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            jj[u] = c + u < a.k_code ? a.code_idx[gr + c + u] : -1;
+            cv[u] = c + u < a.k_code ? a.code_val[gr + c + u] : 0.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
+            else if (jj[u] >= 0) atomicAdd(&row[jj[u]], rc.y * cv[u]);
+          }
         }
       }
     }
@@ -271,7 +280,7 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_rec, dim3(b.n_tiles), dim3(kTileThreads), 0, s, b.splats, b.tile_start,
+  hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.rmap, a.n_regions,
                      a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, a.records, b.status);
   StageTimer::end(kStComposite, s);
