@@ -124,6 +124,50 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
     return res
 
 
+def bench_decode_sweep(lib, P, sg, torch, np, px=1440 * 1080, d=512, reps=5):
+    """Decode alone over codebook sizes M in {64, 128, 256, 512} (D = 512,
+    one 1440x1080 view of coefficients, sparse rows like rendered maps), FP32 /
+    BF16 / FP8 inputs; HIP-event time on the launch stream."""
+    out = {}
+    rng = np.random.default_rng(7)
+    for m in (64, 128, 256, 512):
+        A = rng.random((px, m), dtype=np.float32) * (rng.random((px, m), dtype=np.float32) < 0.1)
+        At = torch.from_numpy(A).cuda()
+        cb = torch.from_numpy(sg.random_codebook(100 + m, m, d)).cuda()
+        ins = {"f32": At, "bf16": At.to(torch.bfloat16),
+               "fp8": (At * 256.0).to(torch.float8_e4m3fn).view(torch.uint8)}
+        row = {}
+        for dt in ("f32", "bf16", "fp8"):
+            out_dt = "f32" if dt == "f32" else "bf16"
+            scl = 256.0 if dt == "fp8" else 1.0
+            P.decode(ins[dt], cb, dt, coeff_scale=scl, out_dtype=out_dt)
+            lib.scoup_stage_timing(1)
+            for _ in range(reps):
+                P.decode(ins[dt], cb, dt, coeff_scale=scl, out_dtype=out_dt)
+            tot, cnt = C_double(), C_int64()
+            lib.scoup_stage_stats(7, C_byref(tot), C_byref(cnt))
+            lib.scoup_stage_timing(0)
+            us = tot.value * 1e3 / max(1, cnt.value)
+            in_b = {"f32": 4, "bf16": 2, "fp8": 1}[dt]
+            by = px * (m * in_b + d * (4 if out_dt == "f32" else 2))
+            row[dt] = {"mpix_s": round(px / (us * 1e-6) / 1e6, 1), "avg_us": round(us, 1),
+                       "tflops": round(2.0 * px * m * d / (us * 1e-6) / 1e12, 1),
+                       "hbm_frac": round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+        out[f"M={m}"] = row
+        log(f"decode sweep M={m}: {row}")
+    return out
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """A plain device copy of known size, for scaling rocprof's FETCH_SIZE /
+    WRITE_SIZE counters (the dispatch appears in the same profile)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +178,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--render-views", type=int, default=100,
                     help="views of the 1440x1080 render workload to time (0 = skip)")
+    ap.add_argument("--decode-sweep", type=int, default=1, help="time decode for M in 64..512 (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy (for scaling HBM counters in a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -203,6 +250,10 @@ def main():
                     per_launch=f"{nc / sc.views.n_views:.4g} contributions x "
                                f"{flops_per_contribution(sc.views.k_code)} flops")
 
+    if args.copy_calibration:
+        copy_calibration(torch)
+    sweep = bench_decode_sweep(lib, P, sg, torch, np) if args.decode_sweep else None
+
     render = None
     if args.render_views > 0:
         render = bench_render_decode(args.render_views, sc.gaussians, lib, P, sg, torch, np)
@@ -237,6 +288,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "render_decode": render,
+        "decode_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 

@@ -147,6 +147,28 @@ scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views
 scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k,
                         int32_t* idx, float* val, void* stream);
 
+/* Dense feature uplift, Eq. 3 (the baseline the sparse uplift replaces):
+ *   features[i*dim + d] = (1/Z_i) sum over (v,p) with region r >= 0 of
+ *                         e_i(v,p) F_r[d],  F_r = sum over code slots c C[j]   (Eq. 4)
+ *   z[i] = Z_i = sum of those e_i(v,p)    (rows with Z_i = 0 are zero)
+ * Same compositing as scoup_uplift; each (Gaussian, region) weight adds a
+ * dim-wide feature instead of k_code coefficients.
+ *   codebook  device float32 [m_atoms*dim];  features device float32 [n*dim];
+ *   z device float32 [n]; 1 <= dim <= 1024.  Workspace from
+ *   scoup_uplift_dense_workspace_bytes (adds R_total*dim floats).          */
+size_t scoup_uplift_dense_workspace_bytes(int64_t n_gaussians, const scoup_views* views, int32_t dim,
+                                          int64_t pair_capacity, int32_t view_batch);
+scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* views, const float* codebook,
+                                int32_t dim, float* features, float* z, int64_t pair_capacity,
+                                int32_t view_batch, void* ws, size_t ws_bytes,
+                                unsigned long long* n_contrib, void* stream);
+
+/* Entropy of each Gaussian's coefficient distribution (App. C.2):
+ * out[i] = -sum_j p_j log p_j with p = acc row i / its sum over positive
+ * entries (natural log, 0 log 0 = 0), 0 for an all-zero row.
+ *   acc  device float32 [n*m] (read only);  out  device float32 [n]        */
+scoup_status scoup_entropy(const float* acc, int64_t n, int32_t m, float* out, void* stream);
+
 /* The full uplift of Algorithm 1: acc is zeroed, accumulated over every view
  * and reduced to k coefficients per Gaussian (Eq. 6, as scoup_topk; fused
  * into the last accumulation pass).  Requires 1 <= k <= min(64, m) and
@@ -233,6 +255,37 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
  * Process-wide state; not meant for concurrent calls from several threads. */
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Several semantic levels in one pass (Sec. 4.1: SAM masks at three
+ * granularities, each level run independently).  The blending weights e of
+ * Eq. 2 do not depend on the level, so one projection / binning / compositing
+ * pass per view serves every level; each level has its own region maps,
+ * codes, accumulator and Top-K output.  Results equal n_levels separate
+ * scoup_uplift calls.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for scoup_uplift_levels (records are kept per level). */
+size_t scoup_uplift_levels_workspace_bytes(int64_t n_gaussians, int32_t n_levels,
+                                           const scoup_views* levels, int64_t pair_capacity,
+                                           int32_t view_batch);
+
+/* levels     host [n_levels], 1 <= n_levels <= 4; identical cameras and m_atoms,
+ *            own region maps, region bases and code tables
+ * k          Top-K size (0: accumulate only, no Top-K)
+ * acc        host array [n_levels] of device float32 [n*m] accumulators (zeroed here)
+ * topk_idx   host array [n_levels] of device int32 [n*k] (ignored if k == 0)
+ * topk_val   host array [n_levels] of device float32 [n*k]
+ * entropy    NULL, or host array [n_levels] of device float32 [n] (NULL entries
+ *            skipped): each Gaussian's row entropy as scoup_entropy, computed
+ *            from the rows while they are on chip
+ * Other arguments and errors as scoup_uplift.                               */
+scoup_status scoup_uplift_levels(const scoup_gaussians* g, int32_t n_levels, const scoup_views* levels,
+                                 int32_t k, float* const* acc, int32_t* const* topk_idx,
+                                 float* const* topk_val, float* const* entropy,
+                                 int64_t pair_capacity, int32_t view_batch,
+                                 void* ws, size_t ws_bytes, unsigned long long* n_contrib,
+                                 void* stream);
 
 /* Thread-local message for the last non-OK status ("" if none). */
 const char* scoup_last_error(void);

@@ -135,6 +135,47 @@ def topk_rows(acc: np.ndarray, k: int):
     return idx, val
 
 
+def dense_uplift(gaussians, views, codebook: np.ndarray):
+    """Dense feature uplift, Eq. 3: f_i = (1/Z_i) sum_{(v,p) in S_i} e_i(v,p) F_v(p)
+    with F_v(p) = W_v(p) C the decoded feature of the pixel's region (Eq. 4)
+    and Z_i = sum e_i(v,p).  Reading: pixels without a region carry no feature
+    and enter neither sum (as in the sparse uplift).  Returns (f (N,D), Z (N,))
+    in FP64; rows with Z_i = 0 are zero."""
+    C = np.asarray(codebook, np.float64)
+    n, d = gaussians.n, C.shape[1]
+    R = views.code_idx.shape[0]
+    F = np.zeros((R, d))
+    for s in range(views.code_idx.shape[1]):
+        j = views.code_idx[:, s]
+        ok = j >= 0
+        F[ok] += views.code_val[ok, s].astype(np.float64)[:, None] * C[j[ok]]
+    f = np.zeros((n, d)); Z = np.zeros(n)
+    cov = covariance3d(gaussians.log_scales, gaussians.quats)
+    for v in range(views.n_views):
+        cam = views.cameras[v]
+        vw = composite_view(project(gaussians, cam, cov), cam.width, cam.height, track_marginal=False)
+        reg = views.region_maps[v].reshape(-1)[vw.pixel]
+        has = reg >= 0
+        gi, e, g = vw.gauss[has], vw.e[has], int(views.region_base[v]) + reg[has].astype(np.int64)
+        np.add.at(f, gi, e[:, None] * F[g])
+        Z += np.bincount(gi, weights=e, minlength=n)
+    f = np.divide(f, Z[:, None], out=np.zeros_like(f), where=Z[:, None] > 0)
+    return f, Z
+
+
+def row_entropy(acc: np.ndarray) -> np.ndarray:
+    """Entropy of each Gaussian's coefficient distribution (App. C.2):
+    H(w_i) = -sum_l p_l log p_l over the row normalised to sum one (natural
+    log, 0 log 0 = 0); an all-zero row has H = 0.  Reading: the accumulated
+    row before Top-K, L1-normalised, as the distribution."""
+    a = np.asarray(acc, np.float64)
+    s = a.sum(axis=1, keepdims=True)
+    p = np.divide(a, s, out=np.zeros_like(a), where=s > 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(p > 0, p * np.log(p), 0.0)
+    return -t.sum(axis=1)
+
+
 def uplift(gaussians, views, k: int):
     """Full uplift: accumulate over all views, then Top-K (Alg. 1)."""
     res = uplift_accumulate(gaussians, views)

@@ -8,7 +8,7 @@ offers torch-facing wrappers (``api``).  Importing it does not load the
 library; the first call does, and raises if the library was not built.
 """
 from .api import (  # noqa: F401
-    DeviceGaussians, DeviceViews, ScoupError, camera_struct, decode, gaussians_to_device,
+    DeviceGaussians, DeviceViews, ScoupError, camera_struct, decode, entropy, gaussians_to_device,
     RenderDecode, render_backward, render_coeff, render_decode, topk, uplift, uplift_accumulate,
-    views_to_device,
+    uplift_dense, uplift_levels, views_to_device,
 )

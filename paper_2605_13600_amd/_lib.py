@@ -36,6 +36,18 @@ SIGNATURES = {
     "scoup_uplift_accumulate": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_void_p, C.c_int32,
                                           C.c_int64, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                           C.c_void_p]),
+    "scoup_uplift_levels_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.POINTER(Views), C.c_int64,
+                                                         C.c_int32]),
+    "scoup_uplift_levels": (C.c_int, [C.POINTER(Gaussians), C.c_int32, C.POINTER(Views), C.c_int32,
+                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_void_p), C.c_int64, C.c_int32, C.c_void_p, C.c_size_t,
+                                      C.c_void_p, C.c_void_p]),
+    "scoup_uplift_dense_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Views), C.c_int32, C.c_int64,
+                                                        C.c_int32]),
+    "scoup_uplift_dense": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                     C.c_void_p]),
+    "scoup_entropy": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
     "scoup_topk": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
     "scoup_uplift": (C.c_int, [C.POINTER(Gaussians), C.POINTER(Views), C.c_int32, C.c_void_p, C.c_void_p,

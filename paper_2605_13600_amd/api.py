@@ -186,6 +186,87 @@ def uplift_accumulate(g: DeviceGaussians, views: DeviceViews, acc: Optional[torc
     return acc, nc
 
 
+def uplift_levels(g: DeviceGaussians, levels: Sequence[DeviceViews], k: int, stream=None, workspace=None,
+                  pair_capacity: int = 0, view_batch: int = 0, entropy: bool = False):
+    """Several semantic levels (same cameras, own region maps and codes) from one
+    compositing pass per view.  Returns ([idx], [val], [acc], n_contrib) -- and
+    [entropy] last if ``entropy`` -- one entry per level."""
+    lib = L.load()
+    dev = g.means.device
+    nl = len(levels)
+    m = levels[0].m_atoms
+    accs = [torch.empty((g.n, m), dtype=torch.float32, device=dev) for _ in range(nl)]
+    idxs = [torch.empty((g.n, max(k, 1)), dtype=torch.int32, device=dev) for _ in range(nl)]
+    vals = [torch.empty((g.n, max(k, 1)), dtype=torch.float32, device=dev) for _ in range(nl)]
+    arr = (L.Views * nl)(*[lv.struct() for lv in levels])
+    P = C.c_void_p * nl
+    pa, pi, pv = P(*[t.data_ptr() for t in accs]), P(*[t.data_ptr() for t in idxs]), P(*[t.data_ptr() for t in vals])
+    ents = [torch.empty(g.n, dtype=torch.float32, device=dev) for _ in range(nl)] if entropy else None
+    pe = P(*[t.data_ptr() for t in ents]) if entropy else None
+    ws = workspace or _workspace(dev)
+    gs = g.struct()
+    key = ("uplift", g.n, levels[0].n_views, int(levels[0]._moff[-1]))
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0), 6 * g.n, 1 << 16)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        vb = int(view_batch) if view_batch else max(1, levels[0].n_views)
+        while vb > 1 and lib.scoup_uplift_levels_workspace_bytes(g.n, nl, arr, cap, vb) > WORKSPACE_LIMIT:
+            vb = (vb + 1) // 2
+        buf = ws.get(lib.scoup_uplift_levels_workspace_bytes(g.n, nl, arr, cap, vb))
+        cnt.zero_()
+        st = lib.scoup_uplift_levels(C.byref(gs), nl, arr, k, pa, pi, pv, pe, cap, vb, _ptr(buf), buf.numel(),
+                                     _ptr(cnt), _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.1) + 4096
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        if entropy:
+            return idxs, vals, accs, int(cnt.item()), ents
+        return idxs, vals, accs, int(cnt.item())
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+def uplift_dense(g: DeviceGaussians, views: DeviceViews, codebook: torch.Tensor, stream=None, workspace=None,
+                 pair_capacity: int = 0, view_batch: int = 0):
+    """Dense feature uplift (Eq. 3) with F_v(p) = W_v(p) C: returns
+    (features (N, D) float32, Z (N,) float32, n_contrib)."""
+    lib = L.load()
+    dev = g.means.device
+    d = int(codebook.shape[1])
+    feat = torch.empty((g.n, d), dtype=torch.float32, device=dev)
+    z = torch.empty(g.n, dtype=torch.float32, device=dev)
+    ws = workspace or _workspace(dev)
+    gs, vs = g.struct(), views.struct()
+    key = ("uplift", g.n, views.n_views, int(views._moff[-1]))
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0), 6 * g.n, 1 << 16)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        vb = int(view_batch) if view_batch else max(1, views.n_views)
+        while vb > 1 and lib.scoup_uplift_dense_workspace_bytes(g.n, C.byref(vs), d, cap, vb) > WORKSPACE_LIMIT:
+            vb = (vb + 1) // 2
+        buf = ws.get(lib.scoup_uplift_dense_workspace_bytes(g.n, C.byref(vs), d, cap, vb))
+        cnt.zero_()
+        st = lib.scoup_uplift_dense(C.byref(gs), C.byref(vs), _ptr(codebook), d, _ptr(feat), _ptr(z), cap, vb,
+                                    _ptr(buf), buf.numel(), _ptr(cnt), _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.1) + 4096
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return feat, z, int(cnt.item())
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
+def entropy(acc: torch.Tensor, stream=None) -> torch.Tensor:
+    """Row entropy of the coefficient distribution (App. C.2) of acc (N, M)."""
+    lib = L.load()
+    n, m = acc.shape
+    out = torch.empty(n, dtype=torch.float32, device=acc.device)
+    _check(lib.scoup_entropy(_ptr(acc), n, m, _ptr(out), _stream(stream)))
+    return out
+
+
 def topk(acc: torch.Tensor, k: int, stream=None):
     """Eq. 6 per row of acc (N, M): (idx int32 (N,k), val float32 (N,k))."""
     lib = L.load()

@@ -236,31 +236,52 @@ int64_t scoup_required_pair_capacity(void) { return g_required_pairs; }
 
 size_t scoup_uplift_workspace_bytes(int64_t n_gaussians, const scoup_views* views, int64_t pair_capacity,
                                     int32_t view_batch) {
-  if (!views || n_gaussians < 0) return 0;
+  return scoup_uplift_levels_workspace_bytes(n_gaussians, 1, views, pair_capacity, view_batch);
+}
+
+size_t scoup_uplift_levels_workspace_bytes(int64_t n_gaussians, int32_t n_levels, const scoup_views* levels,
+                                           int64_t pair_capacity, int32_t view_batch) {
+  if (!levels || n_gaussians < 0 || n_levels < 1 || n_levels > kMaxLevels) return 0;
+  const scoup_views* views = &levels[0];
   if (views->n_views > 0 && !views->cams) return 0;
   if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(6 * n_gaussians, 1 << 16);
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : views->n_views, views->n_views));
-  return bin_layout(n_gaussians, max_tiles_of(views), pair_capacity, vb, vb).total;
+  return bin_layout(n_gaussians, max_tiles_of(views), pair_capacity, vb, vb * n_levels).total;
 }
 
 namespace {
-scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* acc, int32_t accumulate,
-                         int32_t k_top, int32_t* topk_idx, float* topk_val, int64_t pair_capacity,
-                         int32_t view_batch, void* ws, size_t ws_bytes, unsigned long long* n_contrib,
-                         void* stream) {
+scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_views* lvs, float* const* acc,
+                         int32_t accumulate, int32_t k_top, int32_t* const* topk_idx, float* const* topk_val,
+                         float* const* entropy, int64_t pair_capacity, int32_t view_batch, void* ws, size_t ws_bytes,
+                         unsigned long long* n_contrib, void* stream) {
   scoup_status st = check_gaussians(g);
   if (st != SCOUP_OK) return st;
-  if ((st = check_views(v)) != SCOUP_OK) return st;
-  if (v->region_base[v->n_views > 0 ? v->n_views : 0] > 0x7fffffffLL)
-    return fail(SCOUP_E_ARG, "more than 2^31 regions in total");
-  if (g->n > 0 && !acc) return fail(SCOUP_E_ARG, "acc is NULL");
+  if (!lvs) return fail(SCOUP_E_ARG, "views is NULL");
+  if (n_levels < 1 || n_levels > kMaxLevels) return fail(SCOUP_E_ARG, "n_levels must be in [1, 4]");
+  if (!acc) return fail(SCOUP_E_ARG, "acc array is NULL");
+  const scoup_views* v = &lvs[0];
+  for (int l = 0; l < n_levels; ++l) {
+    if ((st = check_views(&lvs[l])) != SCOUP_OK) return st;
+    const scoup_views& w = lvs[l];
+    if (w.n_views != v->n_views || w.m_atoms != v->m_atoms)
+      return fail(SCOUP_E_ARG, "all levels need the same views and m_atoms");
+    for (int i = 0; i < w.n_views; ++i)
+      if (w.cams[i].width != v->cams[i].width || w.cams[i].height != v->cams[i].height ||
+          std::memcmp(&w.cams[i], &v->cams[i], sizeof(scoup_camera)) != 0)
+        return fail(SCOUP_E_ARG, "all levels need the same cameras");
+    if (w.n_views > 0 && w.region_base[w.n_views] > 0x7fffffffLL)
+      return fail(SCOUP_E_ARG, "more than 2^31 regions in total");
+    if (g->n > 0 && !acc[l]) return fail(SCOUP_E_ARG, "acc is NULL");
+    if (k_top > 0 && g->n > 0 && (!topk_idx || !topk_val || !topk_idx[l] || !topk_val[l]))
+      return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
+  }
   if (!ws) return fail(SCOUP_E_ARG, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace must be 256-byte aligned");
   if (pair_capacity < 1 || pair_capacity > 0x7fffffffLL) return fail(SCOUP_E_ARG, "pair_capacity out of range");
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : std::max(1, v->n_views),
                                            std::max(1, v->n_views)));
   const int mt = max_tiles_of(v);
-  const BinLayout L = bin_layout(g->n, mt, pair_capacity, vb, vb);
+  const BinLayout L = bin_layout(g->n, mt, pair_capacity, vb, vb * n_levels);
   if (ws_bytes < L.total) {
     g_required_pairs = pair_capacity;
     return fail(SCOUP_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
@@ -271,22 +292,21 @@ scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* 
   Status* status = reinterpret_cast<Status*>(base + L.status);
   HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
   const size_t acc_bytes = sizeof(float) * (size_t)g->n * (size_t)v->m_atoms;
-  if (!accumulate && acc_bytes) HIP_TRY(hipMemsetAsync(acc, 0, acc_bytes, s));
+  if (!accumulate && acc_bytes)
+    for (int l = 0; l < n_levels; ++l) HIP_TRY(hipMemsetAsync(acc[l], 0, acc_bytes, s));
 
   UpliftViewArgs a{};
   BinArgs& b = a.bin;
   fill_bin(b, g, base, L, pair_capacity, 3, 2048);
-  a.code_idx = v->code_idx; a.code_val = v->code_val;
-  a.k_code = v->k_code; a.m_atoms = v->m_atoms;
-  a.acc = acc;
+  a.n_levels = n_levels;
+  a.m_atoms = v->m_atoms;
   unsigned int* off_all = b.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
-  RowBuildArgs rb{};
-  rb.n = g->n; rb.m_atoms = v->m_atoms; rb.k_code = v->k_code;
-  rb.code_idx = v->code_idx; rb.code_val = v->code_val;
-  rb.r_total = v->n_views > 0 ? v->region_base[v->n_views] : 0;
-  rb.offsets = off_all; rb.records = rec_all; rb.capacity = pair_capacity;
-  rb.acc = acc; rb.status = status;
+  const size_t rec_view = 2 * (size_t)pair_capacity;           // float2 per view and level
+  for (int l = 0; l < n_levels; ++l) {
+    a.lv[l].code_idx = lvs[l].code_idx; a.lv[l].code_val = lvs[l].code_val;
+    a.lv[l].k_code = lvs[l].k_code; a.lv[l].acc = acc[l];
+  }
   const bool want_topk = k_top > 0;
   if (g->n > 0) {
     for (int v0 = 0; v0 < v->n_views; v0 += vb) {
@@ -298,19 +318,35 @@ scoup_status uplift_impl(const scoup_gaussians* g, const scoup_views* v, float* 
         b.tiles_x = (c.width + 7) / 8;
         b.n_tiles = tiles_of(c.width, c.height, 3);
         b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
-        a.records = rec_all + (size_t)j * 2 * (size_t)pair_capacity;
-        a.rmap = v->region_maps + v->map_offsets[i];
-        a.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
-        a.region_base = v->region_base[i];
+        for (int l = 0; l < n_levels; ++l) {
+          a.lv[l].records = rec_all + ((size_t)l * vb + j) * rec_view;
+          a.lv[l].rmap = lvs[l].region_maps + lvs[l].map_offsets[i];
+          a.lv[l].n_regions = (int)(lvs[l].region_base[i + 1] - lvs[l].region_base[i]);
+          a.lv[l].region_base = lvs[l].region_base[i];
+        }
         HIP_TRY(launch_uplift_view(a, s));
       }
-      rb.n_views = nvb;
       const bool last = v0 + vb >= v->n_views;
-      rb.k_top = (want_topk && last) ? k_top : 0;
-      rb.topk_idx = topk_idx; rb.topk_val = topk_val;
-      HIP_TRY(launch_rowbuild(rb, s));
+      for (int l = 0; l < n_levels; ++l) {
+        RowBuildArgs rb{};
+        rb.n = g->n; rb.m_atoms = v->m_atoms; rb.k_code = lvs[l].k_code;
+        rb.code_idx = lvs[l].code_idx; rb.code_val = lvs[l].code_val;
+        rb.r_total = lvs[l].region_base[v->n_views];
+        rb.offsets = off_all; rb.records = rec_all + (size_t)l * vb * rec_view; rb.capacity = pair_capacity;
+        rb.acc = acc[l]; rb.status = status;
+        rb.n_views = nvb;
+        rb.k_top = (want_topk && last) ? k_top : 0;
+        rb.topk_idx = want_topk ? topk_idx[l] : nullptr;
+        rb.topk_val = want_topk ? topk_val[l] : nullptr;
+        rb.entropy = (entropy && last) ? entropy[l] : nullptr;
+        HIP_TRY(launch_rowbuild(rb, s));
+      }
     }
-    if (want_topk && v->n_views == 0) HIP_TRY(launch_topk(acc, g->n, v->m_atoms, k_top, topk_idx, topk_val, s));
+    if (v->n_views == 0)
+      for (int l = 0; l < n_levels; ++l) {
+        if (want_topk) HIP_TRY(launch_topk(acc[l], g->n, v->m_atoms, k_top, topk_idx[l], topk_val[l], s));
+        if (entropy && entropy[l]) HIP_TRY(launch_entropy(acc[l], g->n, v->m_atoms, entropy[l], s));
+      }
   }
   if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
   Status h{};
@@ -332,8 +368,21 @@ scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views
                                      int32_t accumulate, int64_t pair_capacity, int32_t view_batch, void* ws,
                                      size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
   g_err.clear();
-  return uplift_impl(g, v, acc, accumulate, 0, nullptr, nullptr, pair_capacity, view_batch, ws, ws_bytes,
-                     n_contrib, stream);
+  float* accs[1] = {acc};
+  return uplift_impl(g, 1, v, accs, accumulate, 0, nullptr, nullptr, nullptr, pair_capacity, view_batch, ws,
+                     ws_bytes, n_contrib, stream);
+}
+
+scoup_status scoup_uplift_levels(const scoup_gaussians* g, int32_t n_levels, const scoup_views* levels, int32_t k,
+                                 float* const* acc, int32_t* const* topk_idx, float* const* topk_val,
+                                 float* const* entropy, int64_t pair_capacity, int32_t view_batch, void* ws, size_t ws_bytes,
+                                 unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  if (!levels) return fail(SCOUP_E_ARG, "levels is NULL");
+  if (k < 0 || k > 64 || k > levels[0].m_atoms) return fail(SCOUP_E_ARG, "k must be in [0, min(64, m_atoms)]");
+  if (levels[0].m_atoms > 4096) return fail(SCOUP_E_ARG, "m_atoms must be <= 4096");
+  return uplift_impl(g, n_levels, levels, acc, 0, k, topk_idx, topk_val, entropy, pair_capacity, view_batch, ws,
+                     ws_bytes, n_contrib, stream);
 }
 
 scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k, int32_t* idx, float* val,
@@ -350,6 +399,104 @@ scoup_status scoup_topk(const float* acc, int64_t n, int32_t m, int32_t k, int32
   return SCOUP_OK;
 }
 
+size_t scoup_uplift_dense_workspace_bytes(int64_t n_gaussians, const scoup_views* views, int32_t dim,
+                                          int64_t pair_capacity, int32_t view_batch) {
+  if (!views || dim < 1) return 0;
+  const int64_t rt = views->n_views > 0 ? views->region_base[views->n_views] : 0;
+  return align256(4 * (size_t)rt * (size_t)dim) +
+         scoup_uplift_levels_workspace_bytes(n_gaussians, 1, views, pair_capacity, view_batch);
+}
+
+scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, const float* codebook, int32_t dim,
+                                float* features, float* z, int64_t pair_capacity, int32_t view_batch, void* ws,
+                                size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  scoup_status st = check_gaussians(g);
+  if (st != SCOUP_OK) return st;
+  if ((st = check_views(v)) != SCOUP_OK) return st;
+  if (dim < 1 || dim > 1024) return fail(SCOUP_E_ARG, "dim must be in [1, 1024]");
+  if (!codebook || (g->n > 0 && (!features || !z))) return fail(SCOUP_E_ARG, "a dense uplift array is NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  if (pair_capacity < 1 || pair_capacity > 0x7fffffffLL) return fail(SCOUP_E_ARG, "pair_capacity out of range");
+  const long long rt = v->n_views > 0 ? v->region_base[v->n_views] : 0;
+  const size_t fbytes = align256(4 * (size_t)rt * (size_t)dim);
+  const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : std::max(1, v->n_views),
+                                           std::max(1, v->n_views)));
+  const BinLayout L = bin_layout(g->n, max_tiles_of(v), pair_capacity, vb, vb);
+  if (ws_bytes < fbytes + L.total) {
+    g_required_pairs = pair_capacity;
+    return fail(SCOUP_E_WORKSPACE, "workspace too small for this capacity and view batch");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* fbase = static_cast<char*>(ws);
+  float* F = reinterpret_cast<float*>(fbase);
+  char* base = fbase + fbytes;
+  Status* status = reinterpret_cast<Status*>(base + L.status);
+  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  if (g->n > 0) {
+    HIP_TRY(hipMemsetAsync(features, 0, sizeof(float) * (size_t)g->n * dim, s));
+    HIP_TRY(hipMemsetAsync(z, 0, sizeof(float) * (size_t)g->n, s));
+  }
+  HIP_TRY(launch_region_features(v->code_idx, v->code_val, rt, v->k_code, codebook, v->m_atoms, dim, F, status, s));
+  UpliftViewArgs a{};
+  BinArgs& b = a.bin;
+  fill_bin(b, g, base, L, pair_capacity, 3, 2048);
+  a.n_levels = 1;
+  a.m_atoms = v->m_atoms;
+  unsigned int* off_all = b.offsets;
+  float2* rec_all = reinterpret_cast<float2*>(base + L.records);
+  LevelView& lv = a.lv[0];
+  lv.code_idx = v->code_idx; lv.code_val = v->code_val; lv.k_code = v->k_code;
+  lv.acc = features; lv.dense_F = F; lv.dense_d = dim; lv.zsum = z;
+  if (g->n > 0) {
+    for (int v0 = 0; v0 < v->n_views; v0 += vb) {
+      const int nvb = std::min(vb, v->n_views - v0);
+      for (int j = 0; j < nvb; ++j) {
+        const int i = v0 + j;
+        const scoup_camera& c = v->cams[i];
+        b.cam = to_dev(c);
+        b.tiles_x = (c.width + 7) / 8;
+        b.n_tiles = tiles_of(c.width, c.height, 3);
+        b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
+        lv.records = rec_all + (size_t)j * 2 * (size_t)pair_capacity;
+        lv.rmap = v->region_maps + v->map_offsets[i];
+        lv.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
+        lv.region_base = v->region_base[i];
+        HIP_TRY(launch_uplift_view(a, s));
+      }
+      const bool last = v0 + vb >= v->n_views;
+      HIP_TRY(launch_rowbuild_dense(g->n, dim, F, rt, nvb, off_all, rec_all, pair_capacity, features, z, 1,
+                                    last ? 1 : 0, s));
+    }
+    if (v->n_views == 0)
+      HIP_TRY(launch_rowbuild_dense(g->n, dim, F, rt, 0, off_all, rec_all, pair_capacity, features, z, 1, 1, s));
+  }
+  if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
+  Status h{};
+  HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  if (h.any_overflow) {
+    g_required_pairs = (int64_t)h.max_pairs;
+    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(pair_capacity) + " exceeded; need " +
+                                       std::to_string(h.max_pairs));
+  }
+  if (h.data_error & 1u) return fail(SCOUP_E_DATA, "a region id is outside [-1, regions of its view)");
+  if (h.data_error & 2u) return fail(SCOUP_E_DATA, "a code atom index is >= m_atoms");
+  return SCOUP_OK;
+}
+
+scoup_status scoup_entropy(const float* acc, int64_t n, int32_t m, float* out, void* stream) {
+  g_err.clear();
+  if (n < 0) return fail(SCOUP_E_ARG, "n < 0");
+  if (m < 1) return fail(SCOUP_E_ARG, "m must be >= 1");
+  if (n > 0 && (!acc || !out)) return fail(SCOUP_E_ARG, "an entropy array is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_entropy(acc, n, m, out, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SCOUP_OK;
+}
+
 scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* v, int32_t k, float* acc,
                           int32_t* topk_idx, float* topk_val, int64_t pair_capacity, int32_t view_batch, void* ws,
                           size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
@@ -358,8 +505,11 @@ scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* v, int32_
   if (k < 1 || k > 64 || k > v->m_atoms) return fail(SCOUP_E_ARG, "k must be in [1, min(64, m_atoms)]");
   if (v->m_atoms > 4096) return fail(SCOUP_E_ARG, "m_atoms must be <= 4096");
   if (g && g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
-  return uplift_impl(g, v, acc, 0, k, topk_idx, topk_val, pair_capacity, view_batch, ws, ws_bytes, n_contrib,
-                     stream);
+  float* accs[1] = {acc};
+  int32_t* idxs[1] = {topk_idx};
+  float* vals[1] = {topk_val};
+  return uplift_impl(g, 1, v, accs, 0, k, idxs, vals, nullptr, pair_capacity, view_batch, ws, ws_bytes,
+                     n_contrib, stream);
 }
 
 size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int64_t pair_capacity) {

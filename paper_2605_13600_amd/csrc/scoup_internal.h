@@ -47,17 +47,26 @@ int radix_passes(int n_tiles);
 long long radix_blocks(long long capacity);
 long long scan_blocks(long long n);
 
-// One view of the uplift: composite + per-(Gaussian, tile) region records.
-struct UpliftViewArgs {
-  BinArgs bin;
-  const int* rmap;
+// One view of the uplift: composite + per-(Gaussian, block) region records,
+// for up to kMaxLevels region maps (semantic levels) sharing one compositing.
+constexpr int kMaxLevels = 4;
+struct LevelView {
+  const int* rmap;         // this view's region map of the level
   int n_regions;
   long long region_base;
   const int* code_idx;
   const float* code_val;
-  int k_code, m_atoms;
-  float* acc;              // regions beyond a tile's two record slots go here directly
-  float2* records;         // [2 * capacity] (global region id as int bits, weight) of this view
+  int k_code;
+  float* acc;              // regions beyond a block's two record slots go here directly
+  float2* records;         // [2 * capacity] (global region id as int bits, weight)
+  const float* dense_F;    // dense feature uplift: region features [R x dense_d] (else NULL);
+  int dense_d;             //   extra regions then add w F_r to acc (N x dense_d) and w to zsum
+  float* zsum;
+};
+struct UpliftViewArgs {
+  BinArgs bin;
+  int n_levels, m_atoms;
+  LevelView lv[kMaxLevels];
 };
 hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s);
 
@@ -76,6 +85,7 @@ struct RowBuildArgs {
   int k_top;                       // 0: no Top-K
   int* topk_idx;
   float* topk_val;
+  float* entropy;                  // [n] row entropy on the last pass, or NULL
   Status* status;
 };
 hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s);
@@ -125,8 +135,13 @@ hipError_t render_bwd_set_lds_limits();
 hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int m, int d, float* grad_C,
                             hipStream_t s);
 hipError_t decode_set_lds_limits();
-hipError_t launch_uplift_view(const UpliftViewArgs& a, hipStream_t s);
 hipError_t launch_topk(const float* acc, long long n, int m, int k, int* idx, float* val, hipStream_t s);
+hipError_t launch_entropy(const float* acc, long long n, int m, float* out, hipStream_t s);
+hipError_t launch_region_features(const int* code_idx, const float* code_val, long long r_total, int k_code,
+                                  const float* C, int m, int d, float* F, Status* st, hipStream_t s);
+hipError_t launch_rowbuild_dense(long long n, int d, const float* F, long long r_total, int n_views,
+                                 const unsigned int* offsets, const float2* records, long long capacity,
+                                 float* feat, float* zsum, int accumulate, int final_pass, hipStream_t s);
 hipError_t launch_add_contrib(unsigned long long* dst, const Status* st, hipStream_t s);
 
 }  // namespace scoup

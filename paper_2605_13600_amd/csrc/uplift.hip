@@ -38,12 +38,17 @@ namespace scoup {
 constexpr int kBlkSortCap = 2048;
 constexpr int kEStride = 65;
 
+struct LevelSlots {           // per level, per lane
+  int reg, slot;
+  unsigned long long mask0, mask1;
+  bool has2;
+  float rg0, rg1;
+};
+
 __global__ __launch_bounds__(64) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
-    int H, const int* __restrict__ rmap, int n_regions, long long region_base,
-    const int* __restrict__ code_idx, const float* __restrict__ code_val, int k_code, int m_atoms,
-    float* __restrict__ acc, float2* __restrict__ rec, Status* st) {
+    int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   __shared__ float smem[64 * kEStride];       // sort keys (2048 x 8 B) first, then E
   __shared__ GSplat s_g[64];
   __shared__ unsigned int s_id[64];
@@ -57,22 +62,32 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   const int tile_x0 = tx * 8, tile_y0 = ty * 8;
   const int px = tile_x0 + lx, py = tile_y0 + ly;
   const bool inside = px < W && py < H;
-  int reg = -1;
-  if (inside) {
-    reg = rmap[(long long)py * W + px];
-    if (reg < -1 || reg >= n_regions) { atomicOr(&st->data_error, 1u); reg = -1; }
+  // per level: the pixel's region (validated on every pixel, empty blocks
+  // included) and the block's two record regions r0 = region of the first
+  // pixel with one, r1 = first other region
+  LevelSlots ls[kMaxLevels];
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    if (l >= n_levels) break;
+    const LevelView& lv = args.lv[l];
+    int reg = -1;
+    if (inside) {
+      reg = lv.rmap[(long long)py * W + px];
+      if (reg < -1 || reg >= lv.n_regions) { atomicOr(&st->data_error, 1u); reg = -1; }
+    }
+    const unsigned long long any = __ballot(reg >= 0);
+    const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
+    const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
+    const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
+    ls[l].reg = reg;
+    ls[l].slot = reg < 0 ? 3 : reg == r0 ? 0 : reg == r1 ? 1 : 2;
+    ls[l].mask0 = __ballot(ls[l].slot == 0);
+    ls[l].mask1 = __ballot(ls[l].slot == 1);
+    ls[l].has2 = __ballot(ls[l].slot == 2) != 0ull;
+    ls[l].rg0 = __int_as_float(r0 >= 0 ? (int)(lv.region_base + r0) : -1);
+    ls[l].rg1 = __int_as_float(r1 >= 0 ? (int)(lv.region_base + r1) : -1);
   }
-  if (L == 0) return;   // (region ids are validated on every pixel, empty blocks included)
-  // record regions: r0 = region of the first pixel with one, r1 = first other region
-  const unsigned long long any = __ballot(reg >= 0);
-  const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
-  const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
-  const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
-  const int slot = reg < 0 ? 3 : reg == r0 ? 0 : reg == r1 ? 1 : 2;
-  const unsigned long long mask0 = __ballot(slot == 0), mask1 = __ballot(slot == 1);
-  const bool has2 = __ballot(slot == 2) != 0ull;
-  const float rg0 = __int_as_float(r0 >= 0 ? (int)(region_base + r0) : -1);
-  const float rg1 = __int_as_float(r1 >= 0 ? (int)(region_base + r1) : -1);
+  if (L == 0) return;
 
   if (L <= kBlkSortCap) {        // depth order in LDS, written back for the batches
     unsigned long long* sk = reinterpret_cast<unsigned long long*>(smem);
@@ -89,6 +104,10 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   float T = 1.0f;
   bool done = !inside;
   unsigned long long count = 0;
+  bool any_has2 = false;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l)
+    if (l < n_levels) any_has2 = any_has2 || ls[l].has2;
   for (int b0 = 0; b0 < L; b0 += 64) {
     const bool all_done = __ballot(!done) == 0ull;
     const int j = b0 + lane;
@@ -125,21 +144,34 @@ __global__ __launch_bounds__(64) void k_composite_blk(
           contributed |= 1ull << k;
           count += (unsigned long long)__popcll(cm);
           E[k * kEStride + lane] = e;
-          if (has2) {   // third and further regions of the block: straight to the accumulator
-            unsigned long long rm = __ballot(e > 0.0f && slot == 2);
-            const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
-            while (rm) {
-              const int l0 = __ffsll((long long)rm) - 1;
-              const int rr = __builtin_amdgcn_readlane(reg, l0);
-              const unsigned long long same = __ballot(reg == rr) & rm;
-              const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
-              const long long gr = (region_base + rr) * (long long)k_code;
-              for (int c = lane; c < k_code; c += 64) {
-                const int jj = code_idx[gr + c];
-                if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                else if (jj >= 0) atomic_add_f32(&acc[row + (unsigned long long)jj], sum * code_val[gr + c]);
+          if (any_has2) {   // third and further regions of a block: straight to the accumulator
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) {
+              if (l >= n_levels || !ls[l].has2) continue;
+              const LevelView& lv = args.lv[l];
+              const int reg = ls[l].reg;
+              unsigned long long rm = __ballot(e > 0.0f && ls[l].slot == 2);
+              const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
+              while (rm) {
+                const int l0 = __ffsll((long long)rm) - 1;
+                const int rr = __builtin_amdgcn_readlane(reg, l0);
+                const unsigned long long same = __ballot(reg == rr) & rm;
+                const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
+                if (lv.dense_F) {      // dense feature uplift: w F_r and w
+                  const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
+                  const unsigned long long drow = (unsigned long long)s_id[k] * (unsigned long long)lv.dense_d;
+                  for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
+                  if (lane == 0) atomic_add_f32(&lv.zsum[s_id[k]], sum);
+                } else {
+                  const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
+                  for (int c = lane; c < lv.k_code; c += 64) {
+                    const int jj = lv.code_idx[gr + c];
+                    if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+                    else if (jj >= 0) atomic_add_f32(&lv.acc[row + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+                  }
+                }
+                rm &= ~same;
               }
-              rm &= ~same;
             }
           }
         }
@@ -147,22 +179,29 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       }
     }
     __syncthreads();
-    if (lane < nb) {   // every pair's two record slots are written, zero weight included
-      float w0 = 0.0f, w1 = 0.0f;
-      if ((contributed >> lane) & 1ull) {
-        const float* row = E + lane * kEStride;
-#pragma unroll 8
-        for (int p = 0; p < 64; ++p) {
-          const float x = row[p];
-          if ((mask0 >> p) & 1ull) w0 += x;
-          else if ((mask1 >> p) & 1ull) w1 += x;
-        }
-      }
+    if (lane < nb) {   // every pair's two record slots per level are written, zero weight included
+      const bool mine = (contributed >> lane) & 1ull;
+      const float* row = E + lane * kEStride;
       const GSplat g = s_g[lane];
       const int bx0 = g.bx0 >> 3, bx1 = g.bx1 >> 3, by0 = g.by0 >> 3;
       const unsigned int p = off[s_id[lane]] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
-      rec[2ull * p] = make_float2(rg0, w0);
-      rec[2ull * p + 1] = make_float2(rg1, w1);
+#pragma unroll
+      for (int l = 0; l < kMaxLevels; ++l) {
+        if (l >= n_levels) break;
+        float w0 = 0.0f, w1 = 0.0f;
+        if (mine) {
+          const unsigned long long m0 = ls[l].mask0, m1 = ls[l].mask1;
+#pragma unroll 8
+          for (int q = 0; q < 64; ++q) {
+            const float x = row[q];
+            if ((m0 >> q) & 1ull) w0 += x;
+            else if ((m1 >> q) & 1ull) w1 += x;
+          }
+        }
+        float2* rec = args.lv[l].records;
+        rec[2ull * p] = make_float2(ls[l].rg0, w0);
+        rec[2ull * p + 1] = make_float2(ls[l].rg1, w1);
+      }
     }
     __syncthreads();
   }
@@ -202,6 +241,22 @@ __device__ __forceinline__ void topk_row(const float* row, int m, int k, int lan
     out_idx[lane] = sel_i;
     out_val[lane] = sel_i >= 0 ? sel_v / sum : 0.0f;
   }
+}
+
+// Entropy of one row's distribution (App. C.2): H = -sum p log p with
+// p = w / sum w over the strictly positive entries; 0 for an all-zero row.
+__device__ __forceinline__ float row_entropy(const float* row, int m, int lane) {
+  float s = 0.0f;
+  for (int j = lane; j < m; j += 64) s += fmaxf(row[j], 0.0f);
+  s = wave_sum(s);
+  if (!(s > 0.0f)) return 0.0f;
+  const float inv = 1.0f / s;
+  float h = 0.0f;
+  for (int j = lane; j < m; j += 64) {
+    const float p = row[j] * inv;
+    if (p > 0.0f) h -= p * logf(p);
+  }
+  return wave_sum(h);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,6 +311,113 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
       topk_row<NS>(rows + g * stride, M, a.k_top, lane, a.topk_idx + (i0 + g) * a.k_top,
                    a.topk_val + (i0 + g) * a.k_top);
   }
+  if (a.entropy) {
+    for (int g = wave; g < gn; g += 4) {
+      const float h = row_entropy(rows + g * stride, M, lane);
+      if (lane == 0) a.entropy[i0 + g] = h;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense feature uplift (Eq. 3) on the same records: the decoded feature of
+// every region, F_r = sum_slots c C[j] (Eq. 4), then one wave per Gaussian
+// sums w F_r over its records (lanes split the D features) and divides by Z.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_region_features(const int* __restrict__ code_idx,
+                                                         const float* __restrict__ code_val, long long r_total,
+                                                         int k_code, const float* __restrict__ C, int m, int d,
+                                                         float* __restrict__ F, Status* st) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= r_total * d) return;
+  const long long r = t / d;
+  const int c = (int)(t - r * d);
+  float acc = 0.0f;
+  for (int s = 0; s < k_code; ++s) {
+    const int j = code_idx[r * k_code + s];
+    if (j >= m) atomicOr(&st->data_error, 2u);
+    else if (j >= 0) acc = fmaf(code_val[r * k_code + s], C[(long long)j * d + c], acc);
+  }
+  F[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_rowbuild_dense(long long n, int d, const float* __restrict__ F,
+                                                        long long r_total, int n_views,
+                                                        const unsigned int* __restrict__ offsets,
+                                                        const float2* __restrict__ records, long long capacity,
+                                                        float* __restrict__ feat, float* __restrict__ zsum,
+                                                        int accumulate, int final_pass) {
+  const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  constexpr int kMaxPer = 16;                 // d <= 1024
+  float acc[kMaxPer];
+  const int per = (d + 63) / 64;
+  float z = 0.0f;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q) acc[q] = 0.0f;
+  if (accumulate) {   // running sums of earlier view batches (un-normalised)
+#pragma unroll
+    for (int q = 0; q < kMaxPer; ++q)
+      if (q < per && q * 64 + lane < d) acc[q] = feat[i * d + q * 64 + lane];
+    z = zsum[i];
+  }
+  const unsigned int cap = (unsigned int)capacity;
+  for (int v = 0; v < n_views; ++v) {
+    const unsigned int* offv = offsets + (long long)v * (n + 1) + i;
+    const unsigned int lo = min(offv[0], cap), hi = min(offv[1], cap);
+    const float2* recv = records + (long long)v * 2 * capacity;
+    for (unsigned int r = 2 * lo; r < 2 * hi; ++r) {
+      const float2 rc = recv[r];
+      const int reg = __float_as_int(rc.x);
+      if (rc.y == 0.0f || reg < 0 || reg >= r_total) continue;
+      z += rc.y;
+      const float* fr = F + (long long)reg * d;
+#pragma unroll
+      for (int q = 0; q < kMaxPer; ++q)
+        if (q < per && q * 64 + lane < d) acc[q] = fmaf(rc.y, fr[q * 64 + lane], acc[q]);
+    }
+  }
+  const float sc = final_pass ? (z > 0.0f ? 1.0f / z : 0.0f) : 1.0f;
+#pragma unroll
+  for (int q = 0; q < kMaxPer; ++q)
+    if (q < per && q * 64 + lane < d) feat[i * d + q * 64 + lane] = acc[q] * sc;
+  if (lane == 0 && zsum) zsum[i] = z;
+}
+
+hipError_t launch_region_features(const int* code_idx, const float* code_val, long long r_total, int k_code,
+                                  const float* C, int m, int d, float* F, Status* st, hipStream_t s) {
+  const long long tot = r_total * d;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_region_features, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, code_idx, code_val,
+                     r_total, k_code, C, m, d, F, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowbuild_dense(long long n, int d, const float* F, long long r_total, int n_views,
+                                 const unsigned int* offsets, const float2* records, long long capacity,
+                                 float* feat, float* zsum, int accumulate, int final_pass, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  StageTimer::begin(kStRowBuild, s);
+  hipLaunchKernelGGL(k_rowbuild_dense, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, d, F, r_total, n_views,
+                     offsets, records, capacity, feat, zsum, accumulate, final_pass);
+  StageTimer::end(kStRowBuild, s);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_entropy(const float* __restrict__ acc, long long n, int m,
+                                                 float* __restrict__ out) {
+  const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const float h = row_entropy(acc + row * (long long)m, m, lane);
+  if (lane == 0) out[row] = h;
+}
+
+hipError_t launch_entropy(const float* acc, long long n, int m, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_entropy, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, acc, n, m, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -281,8 +443,8 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
   hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
-                     b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.rmap, a.n_regions,
-                     a.region_base, a.code_idx, a.code_val, a.k_code, a.m_atoms, a.acc, a.records, b.status);
+                     b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
+                     a, b.status);
   StageTimer::end(kStComposite, s);
   return hipGetLastError();
 }

@@ -171,3 +171,62 @@ def test_full_size_scene_sampled_rows():
     st = PT.check_topk(idx[rows], val[rows], ref.acc, ref.amb, sc.k_top)
     print(f"[scene-2views] contrib={nc} acc={sa} topk={st}", flush=True)
     assert (ref.acc.sum(1) > 0).sum() > 200
+
+
+def test_three_semantic_levels_in_one_pass():
+    """Three region maps over the same cameras (4, 8 and 16 Voronoi cells, own
+    codes) uplifted in one compositing pass; each level matches the oracle run
+    on that level alone."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    levels = [sg.make_views(500 + s, sc.views.cameras, s, 64, 4, hole_sites=1 if s == 8 else 0)
+              for s in (4, 8, 16)]
+    dg = P.gaussians_to_device(sc.gaussians)
+    idxs, vals, accs, nc, ents = P.uplift_levels(dg, [P.views_to_device(v) for v in levels], 4, entropy=True)
+    torch.cuda.synchronize()
+    for lvl, v in enumerate(levels):
+        ref = OU.uplift_accumulate(sc.gaussians, v)
+        sa = PT.check_acc(accs[lvl].cpu().numpy(), ref.acc, ref.amb)
+        # entropy of the fused pass, against the oracle on the oracle's rows (1e-4 abs:
+        # float32 rows and logs; rows with ambiguity mass are left out)
+        He = OU.row_entropy(ref.acc)
+        okr = ref.amb.sum(1) == 0
+        assert np.allclose(ents[lvl].cpu().numpy()[okr], He[okr], atol=1e-4, rtol=1e-4)
+        st = PT.check_topk(idxs[lvl].cpu().numpy(), vals[lvl].cpu().numpy(), ref.acc, ref.amb, 4)
+        assert abs(nc - ref.n_contrib) <= ref.count_slack
+        print(f"[level {lvl}] acc={sa} topk={st}")
+
+
+def test_entropy_kernel_against_oracle():
+    """Row entropy (App. C.2) on a seeded float32 matrix with zero rows and
+    one-hot rows, against the oracle on the same float32 values."""
+    require_gpu()
+    rng = np.random.default_rng(9)
+    A = (rng.random((3000, 256)) * (rng.random((3000, 256)) < 0.05)).astype(np.float32)
+    A[:5] = 0
+    A[5:9] = 0; A[5:9, 3] = 1.5
+    H = P.entropy(torch.from_numpy(A).cuda()).cpu().numpy()
+    R = OU.row_entropy(A.astype(np.float64))
+    assert (H[:9] == 0).all()
+    assert np.allclose(H, R, rtol=1e-5, atol=2e-6)
+
+
+@pytest.mark.parametrize("d", [64, 512])
+def test_dense_feature_uplift_against_oracle(d):
+    """Eq. 3 on the same engine: features within 1e-5 relative (row norm) plus
+    the ambiguity mass carried through the decoded features; Z within 1e-5."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45), hole_sites=1)
+    C = sg.random_codebook(31, 64, d)
+    dg, dv = to_device(sc.gaussians, sc.views)
+    feat, z, nc = P.uplift_dense(dg, dv, torch.from_numpy(C).cuda())
+    torch.cuda.synchronize()
+    f_ref, z_ref = OU.dense_uplift(sc.gaussians, sc.views, C)
+    amb = OU.uplift_accumulate(sc.gaussians, sc.views).amb
+    zr = z.cpu().numpy().astype(np.float64)
+    ok = amb.sum(1) == 0
+    assert np.allclose(zr[ok], z_ref[ok], rtol=1e-5, atol=1e-9)
+    fg = feat.cpu().numpy().astype(np.float64)
+    nrm = np.linalg.norm(f_ref, axis=1)
+    err = np.linalg.norm(fg - f_ref, axis=1)
+    assert (err[ok] <= 1e-5 * nrm[ok] + 1e-7).all(), float((err[ok] / np.maximum(nrm[ok], 1e-30)).max())

@@ -377,3 +377,36 @@ def test_planted_depth_order_is_caught(monkeypatch):
     lst = _pixel_lists(vw, cam.width)[(4, 4)]
     case = GOLD["two_gaussians_one_pixel"]["cases"][0]
     assert lst[1][1] != pytest.approx(case["e_back"], abs=1e-6)
+
+
+def test_row_entropy_pins():
+    from scipy.stats import entropy as sp_entropy
+    rng = np.random.default_rng(3)
+    A = rng.random((50, 40)) * (rng.random((50, 40)) < 0.4)
+    A[0] = 0
+    A[1] = 0; A[1, 7] = 2.5
+    A[2] = 1.0
+    H = OU.row_entropy(A)
+    assert H[0] == 0.0 and H[1] == 0.0
+    assert H[2] == pytest.approx(math.log(40), rel=1e-14)
+    for r in range(3, 50):
+        assert H[r] == pytest.approx(sp_entropy(A[r]), rel=1e-12, abs=1e-14)
+    assert np.allclose(OU.row_entropy(7.0 * A), H, rtol=1e-13)   # scale invariant
+
+
+def test_dense_uplift_oracle_equals_sparse_times_codebook():
+    """Eq. 3 with F = W C is the untruncated sparse uplift (Eq. 5) decoded by C:
+    f_i = (acc_i / Z_i) C, with Z_i the row sum of acc when codes sum to one."""
+    g, views = S.small_scene(23, n=60, m=8, k=3)
+    # exact convex codes so that row sums equal Z
+    val = views.code_val.astype(np.float64)
+    val /= val.sum(1, keepdims=True)
+    vv = sg.Views(views.cameras, views.region_maps, views.region_base, views.code_idx, val, 8)
+    C = sg.random_codebook(4, 8, 5).astype(np.float64)
+    f, Z = OU.dense_uplift(g, vv, C)
+    acc = OU.uplift_accumulate(g, vv).acc
+    t = Z > 0
+    assert t.sum() > 20
+    assert np.allclose(acc.sum(1), Z, rtol=1e-12)
+    assert np.allclose(f[t], (acc[t] / Z[t, None]) @ C, atol=1e-12)
+    assert (f[~t] == 0).all()
