@@ -158,6 +158,48 @@ def bench_decode_sweep(lib, P, sg, torch, np, px=1440 * 1080, d=512, reps=5):
     return out
 
 
+def bench_levels_and_dense(sc, P, sg, torch, np, dense_views=20):
+    """Three semantic levels in one pass vs three single-level uplifts (all
+    views), and the dense feature uplift (Eq. 3, D = 512) vs the sparse uplift
+    on the first ``dense_views`` views."""
+    out = {}
+    v = sc.views
+    lv2 = sg.make_views(3001, v.cameras, 60, v.m_atoms, v.k_code)
+    lv3 = sg.make_views(3002, v.cameras, 240, v.m_atoms, v.k_code)
+    dg = P.gaussians_to_device(sc.gaussians)
+    dvs = [P.views_to_device(x) for x in (v, lv2, lv3)]
+    ws = P.api.Workspace()
+    k = sc.k_top
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    t3, r3 = timed(lambda: P.uplift_levels(dg, dvs, k, workspace=ws))
+    t1 = 0.0
+    for dv in dvs:
+        t, _ = timed(lambda dv=dv: P.uplift(dg, dv, k, workspace=ws))
+        t1 += t
+    out["levels"] = {"workload": "3 levels (120 / 60 / 240 regions per view), all views",
+                     "one_pass_ms": round(t3 * 1e3, 2), "three_uplifts_ms": round(t1 * 1e3, 2),
+                     "speedup": round(t1 / t3, 2), "contributions": r3[3]}
+    log(f"levels: {out['levels']}")
+    sub = sg.subset_views(v, range(min(dense_views, v.n_views)))
+    dsub = P.views_to_device(sub)
+    cb = torch.from_numpy(sg.random_codebook(3003, v.m_atoms, 512)).cuda()
+    ts, _ = timed(lambda: P.uplift(dg, dsub, k, workspace=ws))
+    td, _ = timed(lambda: P.uplift_dense(dg, dsub, cb, workspace=ws))
+    out["dense_vs_sparse"] = {"workload": f"first {sub.n_views} views, D=512 vs M={v.m_atoms}, K_code={v.k_code}",
+                              "sparse_ms": round(ts * 1e3, 2), "dense_ms": round(td * 1e3, 2),
+                              "dense_over_sparse": round(td / ts, 2)}
+    log(f"dense vs sparse: {out['dense_vs_sparse']}")
+    return out
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling rocprof's FETCH_SIZE /
     WRITE_SIZE counters (the dispatch appears in the same profile)."""
@@ -179,6 +221,8 @@ def main():
     ap.add_argument("--render-views", type=int, default=100,
                     help="views of the 1440x1080 render workload to time (0 = skip)")
     ap.add_argument("--decode-sweep", type=int, default=1, help="time decode for M in 64..512 (0 = skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="three-level pass and dense-vs-sparse uplift sections (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling HBM counters in a profile)")
     args = ap.parse_args()
@@ -253,6 +297,7 @@ def main():
     if args.copy_calibration:
         copy_calibration(torch)
     sweep = bench_decode_sweep(lib, P, sg, torch, np) if args.decode_sweep else None
+    extras = bench_levels_and_dense(sc, P, sg, torch, np) if args.extras else None
 
     render = None
     if args.render_views > 0:
@@ -289,6 +334,7 @@ def main():
         "cpu_baseline": cpu,
         "render_decode": render,
         "decode_sweep": sweep,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -24,7 +24,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(
     const int* __restrict__ topk_idx, int K, int M, int sort_cap, const float* __restrict__ dW,
     float* __restrict__ grad_val, Status* st) {
   extern __shared__ float rows[];          // 64 * (M+1) floats; aliased by the sort keys first
-  __shared__ GSplat s_g[64];
   __shared__ unsigned int s_id[64];
   __shared__ int s_ti[64 * kBwdKMax];
   if (st->view_overflow) return;
@@ -65,16 +64,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   for (int b0 = 0; b0 < L; b0 += 64) {
     if (__ballot(!done) == 0ull) break;
     const int j = b0 + lane;
+    SplatLane mine;
     if (j < L) {
       const unsigned int id = (unsigned int)keys[start + j];
-      s_g[lane] = splats[id];
+      mine.load(splats[id]);
       s_id[lane] = id;
       for (int k = 0; k < K; ++k) s_ti[lane * K + k] = topk_idx[(long long)id * K + k];
     }
     __syncthreads();
     const int nb = min(64, L - b0);
     for (int k = 0; k < nb; ++k) {
-      const GSplat g = s_g[k];
+      const SplatLane g = mine.bcast(k);
       const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
       const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
@@ -93,14 +93,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         }
       }
       if (__ballot(e > 0.0f)) {
-        float mine = 0.0f;
+        float gsum = 0.0f;
         for (int kk = 0; kk < K; ++kk) {
           const int jj = s_ti[k * K + kk];
           const float prod = (e > 0.0f && jj >= 0 && jj < M) ? e * myrow[jj] : 0.0f;
           const float sum = wave_sum(prod);
-          if (lane == kk) mine = sum;
+          if (lane == kk) gsum = sum;
         }
-        if (lane < K && mine != 0.0f) atomic_add_f32(&grad_val[(long long)s_id[k] * K + lane], mine);
+        if (lane < K && gsum != 0.0f) atomic_add_f32(&grad_val[(long long)s_id[k] * K + lane], gsum);
       }
       if (__ballot(!done) == 0ull) break;
     }

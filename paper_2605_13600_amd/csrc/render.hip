@@ -24,7 +24,6 @@ __global__ __launch_bounds__(64) void k_render_coeff(
     int sort_cap, OutT* __restrict__ out, float out_scale, float* __restrict__ t_final,
     Status* st) {
   extern __shared__ float rows[];          // 64 * (M+1) floats; aliased by the sort keys first
-  __shared__ GSplat s_g[64];
   __shared__ int s_ti[64 * kRenderKMax];
   __shared__ float s_tv[64 * kRenderKMax];
   if (st->view_overflow) return;
@@ -60,9 +59,10 @@ __global__ __launch_bounds__(64) void k_render_coeff(
   for (int b0 = 0; b0 < L; b0 += 64) {
     if (__ballot(!done) == 0ull) break;
     const int j = b0 + lane;
+    SplatLane mine;
     if (j < L) {
       const unsigned int id = (unsigned int)keys[start + j];
-      s_g[lane] = splats[id];
+      mine.load(splats[id]);
       for (int k = 0; k < K; ++k) {
         s_ti[lane * K + k] = topk_idx[(long long)id * K + k];
         s_tv[lane * K + k] = topk_val[(long long)id * K + k];
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64) void k_render_coeff(
     __syncthreads();
     const int nb = min(64, L - b0);
     for (int k = 0; k < nb; ++k) {
-      const GSplat g = s_g[k];
+      const SplatLane g = mine.bcast(k);
       const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
       const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;

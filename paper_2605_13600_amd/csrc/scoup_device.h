@@ -33,6 +33,29 @@ struct __align__(16) GSplat {
 };
 static_assert(sizeof(GSplat) == 48, "GSplat layout");
 
+// The fields of a GSplat that compositing needs, held by the lane that loaded
+// it; bcast(k) reads lane k's copy into every lane via SGPRs (v_readlane), so
+// the sequential per-Gaussian loop does not wait on LDS.
+struct SplatLane {
+  int ix, iy;
+  float fx, fy, l00, l10, l11, opacity;
+  __device__ __forceinline__ void load(const GSplat& g) {
+    ix = g.ix; iy = g.iy; fx = g.fx; fy = g.fy; l00 = g.l00; l10 = g.l10; l11 = g.l11; opacity = g.opacity;
+  }
+  __device__ __forceinline__ SplatLane bcast(int k) const {
+    SplatLane r;
+    r.ix = __builtin_amdgcn_readlane(ix, k);
+    r.iy = __builtin_amdgcn_readlane(iy, k);
+    r.fx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fx), k));
+    r.fy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fy), k));
+    r.l00 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l00), k));
+    r.l10 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l10), k));
+    r.l11 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l11), k));
+    r.opacity = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(opacity), k));
+    return r;
+  }
+};
+
 // Small per-call status block in the workspace.
 struct Status {
   unsigned int total_pairs;     // pairs of the current view

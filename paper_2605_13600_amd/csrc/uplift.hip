@@ -50,8 +50,6 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   __shared__ float smem[64 * kEStride];       // sort keys (2048 x 8 B) first, then E
-  __shared__ GSplat s_g[64];
-  __shared__ unsigned int s_id[64];
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -112,16 +110,19 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const bool all_done = __ballot(!done) == 0ull;
     const int j = b0 + lane;
     const int nb = min(64, L - b0);
+    SplatLane mine;
+    unsigned int my_id = 0;
+    int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
     if (j < L) {
-      const unsigned int id = (unsigned int)keys[start + j];
-      s_id[lane] = id;
-      s_g[lane] = splats[id];
+      my_id = (unsigned int)keys[start + j];
+      const GSplat gg = splats[my_id];
+      mine.load(gg);
+      own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
     }
-    __syncthreads();
     unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
     if (!all_done) {
       for (int k = 0; k < nb; ++k) {
-        const GSplat g = s_g[k];
+        const SplatLane g = mine.bcast(k);
         const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
         const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
         const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(64) void k_composite_blk(
               const LevelView& lv = args.lv[l];
               const int reg = ls[l].reg;
               unsigned long long rm = __ballot(e > 0.0f && ls[l].slot == 2);
-              const unsigned long long row = (unsigned long long)s_id[k] * (unsigned long long)m_atoms;
+              const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
+              const unsigned long long row = (unsigned long long)idk * (unsigned long long)m_atoms;
               while (rm) {
                 const int l0 = __ffsll((long long)rm) - 1;
                 const int rr = __builtin_amdgcn_readlane(reg, l0);
@@ -159,9 +161,9 @@ __global__ __launch_bounds__(64) void k_composite_blk(
                 const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
                 if (lv.dense_F) {      // dense feature uplift: w F_r and w
                   const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
-                  const unsigned long long drow = (unsigned long long)s_id[k] * (unsigned long long)lv.dense_d;
+                  const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
                   for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
-                  if (lane == 0) atomic_add_f32(&lv.zsum[s_id[k]], sum);
+                  if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
                 } else {
                   const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
                   for (int c = lane; c < lv.k_code; c += 64) {
@@ -180,16 +182,15 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     }
     __syncthreads();
     if (lane < nb) {   // every pair's two record slots per level are written, zero weight included
-      const bool mine = (contributed >> lane) & 1ull;
+      const bool had = (contributed >> lane) & 1ull;
       const float* row = E + lane * kEStride;
-      const GSplat g = s_g[lane];
-      const int bx0 = g.bx0 >> 3, bx1 = g.bx1 >> 3, by0 = g.by0 >> 3;
-      const unsigned int p = off[s_id[lane]] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+      const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
+      const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
 #pragma unroll
       for (int l = 0; l < kMaxLevels; ++l) {
         if (l >= n_levels) break;
         float w0 = 0.0f, w1 = 0.0f;
-        if (mine) {
+        if (had) {
           const unsigned long long m0 = ls[l].mask0, m1 = ls[l].mask1;
 #pragma unroll 8
           for (int q = 0; q < 64; ++q) {
