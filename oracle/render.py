@@ -63,3 +63,12 @@ def relevancy(features: np.ndarray, query: np.ndarray, canon: np.ndarray,
     fq = features @ np.asarray(query, np.float64)
     fc = features @ np.asarray(canon, np.float64).T
     return np.min(1.0 / (1.0 + np.exp(temperature * (fc - fq[:, None]))), axis=1)
+
+
+def relevancy_map(coeff: np.ndarray, codebook: np.ndarray, queries: np.ndarray, canon: np.ndarray,
+                  temperature: float = 10.0) -> np.ndarray:
+    """Relevancy of every pixel to every query (App. B) on the decoded
+    features of Eq. 8: R[p, q] = relevancy(F, queries[q], canon)[p] with
+    F = W_hat C in FP64.  Returns [P, Q] float64."""
+    F = decode(coeff, codebook)
+    return np.stack([relevancy(F, qv, canon, temperature) for qv in np.asarray(queries, np.float64)], axis=1)

@@ -410,3 +410,67 @@ def test_dense_uplift_oracle_equals_sparse_times_codebook():
     assert np.allclose(acc.sum(1), Z, rtol=1e-12)
     assert np.allclose(f[t], (acc[t] / Z[t, None]) @ C, atol=1e-12)
     assert (f[~t] == 0).all()
+
+
+# ---------------------------------------------------------------- relevancy (App. B)
+def _orthonormal(rng, n, d):
+    q, _ = np.linalg.qr(rng.standard_normal((d, n)))
+    return q.T                                           # n orthonormal rows
+
+
+def test_relevancy_closed_forms():
+    """Special cases of the App. B score that reduce to the logistic function
+    (scipy's expit): a feature along the query with one canonical vector
+    orthogonal to both gives expit(a |F|); a zero feature gives one half."""
+    from scipy.special import expit
+    rng = np.random.default_rng(11)
+    q, c1, c2, c3 = _orthonormal(rng, 4, 16)
+    for s in (1.0, -1.0, 0.1, 0.37):
+        F = (s * q)[None]
+        r = OR.relevancy(F, q, c1[None])
+        assert r[0] == pytest.approx(expit(10.0 * s), rel=1e-14)           # a = 10
+        assert OR.relevancy(F, q, c1[None], temperature=3.0)[0] == pytest.approx(expit(3.0 * s), rel=1e-14)
+    assert OR.relevancy(np.zeros((1, 16)), q, np.stack([c1, c2]))[0] == 0.5
+    # the minimum over canonical vectors: a canonical equal to the query caps the score at 1/2
+    F = (0.8 * q + 0.3 * c2)[None]
+    r = OR.relevancy(F, q, np.stack([c1, q, c3]))
+    assert r[0] == pytest.approx(0.5, abs=0)
+    # the least favourable canonical vector decides: F.c2 = 0.3 > F.c1 = 0
+    assert OR.relevancy(F, q, np.stack([c1, c2]))[0] == pytest.approx(expit(10.0 * (0.8 - 0.3)), rel=1e-14)
+
+
+def test_relevancy_invariants():
+    """With one canonical vector, swapping it with the query maps R to 1 - R;
+    the score is independent of the order of the canonical vectors and never
+    exceeds the score against any single one of them."""
+    rng = np.random.default_rng(12)
+    F = rng.standard_normal((200, 24)) * 0.3
+    q = rng.standard_normal(24); q /= np.linalg.norm(q)
+    cs = rng.standard_normal((4, 24)); cs /= np.linalg.norm(cs, axis=1, keepdims=True)
+    r1 = OR.relevancy(F, q, cs[:1]); r1s = OR.relevancy(F, cs[0], q[None])
+    assert np.allclose(r1 + r1s, 1.0, atol=1e-15)
+    r = OR.relevancy(F, q, cs)
+    assert np.allclose(r, OR.relevancy(F, q, cs[::-1]), rtol=1e-14, atol=0)
+    for k in range(4):
+        assert (r <= OR.relevancy(F, q, cs[k:k + 1]) * (1 + 1e-13)).all()
+    assert ((r > 0) & (r < 1)).all()
+    # monotone in the query-minus-canonical similarity
+    one = OR.relevancy(F, q, cs[:1])
+    d = F @ q - F @ cs[0]
+    assert (np.diff(one[np.argsort(d)]) >= 0).all()
+
+
+def test_relevancy_map_is_decode_then_score():
+    """The per-query map decodes once (Eq. 8) and scores each query; a
+    coefficient row that is one-hot on atom j scores the codebook row C_j."""
+    rng = np.random.default_rng(13)
+    C = sg.random_codebook(5, 12, 20).astype(np.float64)
+    qs = sg.random_unit_vectors(6, 3, 20); cs = sg.random_unit_vectors(7, 4, 20)
+    W = np.eye(12)
+    R = OR.relevancy_map(W, C, qs, cs)
+    assert R.shape == (12, 3)
+    for j in range(12):
+        for t in range(3):
+            assert R[j, t] == pytest.approx(OR.relevancy(C[j:j + 1], qs[t], cs)[0], rel=1e-14)
+    W2 = rng.random((30, 12))
+    assert np.allclose(OR.relevancy_map(W2, C, qs, cs)[:, 1], OR.relevancy(W2 @ C, qs[1], cs), rtol=1e-13)
