@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 not used
 STAGES = ["project", "pair_scan", "emit", "tile_sort", "composite", "topk",
-          "render", "decode", "render_backward", "backward_gemm", "row_build"]
+          "render", "decode", "render_backward", "backward_gemm", "row_build", "relevancy", "relevancy_fold"]
 
 
 def log(msg):
@@ -73,7 +73,8 @@ def cpu_baseline(sc, rows=192):
 def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
     """Render (Eq. 7) + decode (Eq. 8) of the 1M-Gaussian scene with synthetic
     Top-8 over M=256, codebook 256x512, on the first ``n_views`` of 100 orbit
-    views at 1440x1080; FP32, BF16 and FP8 decode inputs."""
+    views at 1440x1080; FP32, BF16 and FP8 decode inputs.  Also the query
+    path: render + fused decode/relevancy (App. B) for 16 query vectors."""
     m, d, k = 256, 512, 8
     cams = sg.orbit_cameras(2002, 100, 12.0, 1.0, 4.0, 1.0, 0.5, 1440, 1080, 60.0)[:n_views]
     ti, tv = sg.random_topk(2003, gaussians.n, m, k)
@@ -81,6 +82,9 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
     dg = P.gaussians_to_device(gaussians)
     dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
     dC = torch.from_numpy(cb).cuda()
+    n_q = 16
+    dQ = torch.from_numpy(sg.random_unit_vectors(2005, n_q, d)).cuda()
+    dCanon = torch.from_numpy(sg.random_unit_vectors(2006, 4, d)).cuda()
     px = 1440 * 1080
     res = {"workload": f"render+decode: {gaussians.n} Gaussians, Top-{k} over M={m}, codebook {m}x{d}, "
                        f"{n_views} views 1440x1080", "views": n_views}
@@ -120,6 +124,30 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
             "decode_mfma_ceiling": round(min(1.0, (flops / bytes_) / (pk * 1e12 / (HBM_PEAK_GBS * 1e9))), 4),
             "contributions_per_view": nc,
         }
+        # query path: render + fused decode/relevancy (App. B), 16 queries, 4 canonical vectors
+        R = P.relevancy(W, dC, dQ, dCanon, dt, coeff_scale=scl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for cam in cams:
+            W, _, nc, scl = P.render_coeff(dg, dti, dtv, cam, m, dtype=dt, want_t_final=False)
+            R = P.relevancy(W, dC, dQ, dCanon, dt, coeff_scale=scl)
+        torch.cuda.synchronize()
+        t_rr = time.perf_counter() - t0
+        lib.scoup_stage_timing(1)
+        for _ in range(n_views):
+            R = P.relevancy(W, dC, dQ, dCanon, dt, coeff_scale=scl)
+        lib.scoup_stage_stats(11, C_byref(tot), C_byref(cnt))
+        rel_us = tot.value * 1e3 / max(1, cnt.value)
+        lib.scoup_stage_stats(12, C_byref(tot), C_byref(cnt))
+        prep_us = tot.value * 1e3 / max(1, cnt.value)
+        lib.scoup_stage_timing(0)
+        rel_bytes = px * (m * in_b[dt] + n_q * 4)
+        res[dt].update({
+            "render_relevancy_mpix_s": round(px * n_views / t_rr / 1e6, 2),
+            "relevancy_avg_us": round(rel_us, 2), "relevancy_fold_avg_us": round(prep_us, 2),
+            "relevancy_hbm_gbs": round(rel_bytes / (rel_us * 1e-6) / 1e9, 1),
+            "relevancy_hbm_frac": round(rel_bytes / (rel_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+        })
         log(f"render+decode {dt}: {res[dt]}")
     return res
 

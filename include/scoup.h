@@ -222,6 +222,31 @@ scoup_status scoup_decode(const void* coeff, scoup_dtype in_dtype, float coeff_s
                           int32_t m_atoms, const float* codebook, int32_t dim, void* features,
                           scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes for scoup_relevancy (the codebook folded into the query
+ * and canonical vectors, in MFMA operand order).                            */
+size_t scoup_relevancy_workspace_bytes(int32_t m_atoms, int32_t n_queries, scoup_dtype in_dtype);
+
+/* Relevancy of App. B on the decoded features of Eq. 8, without writing them:
+ *   scores[p*n_queries + q] = min over c < n_canon of
+ *       1 / (1 + exp(temperature * (F(p).canon_c - F(p).query_q)))
+ * with F(p) = (1/coeff_scale) coeff[p, :] codebook, i.e. the exponential
+ * ratio of the appendix (temperature 10 there, 4 canonical phrases).  The
+ * dot products are formed as coeff[p, :] (codebook query) with the folded
+ * vectors computed in FP64; the per-pixel contraction runs on MFMA (float32
+ * for F32 maps; bfloat16 with a two-term bfloat16 split of the folded vectors
+ * for BF16 and FP8 maps), float32 accumulation and epilogue.
+ *   coeff     device [n_pixels*m_atoms] of in_dtype (the map of scoup_render_coeff)
+ *   codebook  device float32 [m_atoms*dim]
+ *   queries   device float32 [n_queries*dim]
+ *   canon     device float32 [n_canon*dim]
+ *   scores    device float32 [n_pixels*n_queries]
+ * Requires 1 <= m_atoms <= 4096, 1 <= dim <= 4096, 1 <= n_queries <= 1024,
+ * 1 <= n_canon <= 4 and a finite temperature > 0 (else SCOUP_E_ARG).        */
+scoup_status scoup_relevancy(const void* coeff, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                             int32_t m_atoms, const float* codebook, int32_t dim, const float* queries,
+                             int32_t n_queries, const float* canon, int32_t n_canon, float temperature,
+                             float* scores, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for scoup_render_backward. */
 size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam,
                                              int32_t m_atoms, int32_t dim, int64_t pair_capacity);
@@ -251,7 +276,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
  * success and -1 for an unknown stage.  Stage ids:
  *   0 project  1 pair scan  2 emit  3 tile sort  4 composite
  *   5 top-k    6 render     7 decode  8 render backward  9 backward GEMMs
- *   10 accumulator row build
+ *   10 accumulator row build  11 relevancy  12 relevancy vector folding
  * Process-wide state; not meant for concurrent calls from several threads. */
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);

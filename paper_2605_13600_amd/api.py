@@ -349,6 +349,26 @@ def decode(coeff: torch.Tensor, codebook: torch.Tensor, in_dtype: str = "bf16", 
     return out
 
 
+def relevancy(coeff: torch.Tensor, codebook: torch.Tensor, queries: torch.Tensor, canon: torch.Tensor,
+              in_dtype: str = "bf16", coeff_scale: float = 1.0, temperature: float = 10.0, stream=None,
+              workspace: Optional[Workspace] = None) -> torch.Tensor:
+    """App. B relevancy of every pixel to every query on the decoded features
+    coeff @ codebook, without forming them.  ``coeff`` is (..., M) in
+    ``in_dtype`` storage; ``queries`` (Q, D) and ``canon`` (n_canon <= 4, D)
+    are float32.  Returns (..., Q) float32 scores."""
+    lib = L.load()
+    m, d = codebook.shape
+    P = coeff.numel() // m
+    q = int(queries.shape[0])
+    out = torch.empty((*coeff.shape[:-1], q), dtype=torch.float32, device=coeff.device)
+    ws = workspace or Workspace(coeff.device)
+    buf = ws.get(lib.scoup_relevancy_workspace_bytes(m, q, _DT[in_dtype]))
+    _check(lib.scoup_relevancy(_ptr(coeff), _DT[in_dtype], float(coeff_scale), P, m, _ptr(codebook), d,
+                               _ptr(queries), q, _ptr(canon), int(canon.shape[0]), float(temperature),
+                               _ptr(out), _ptr(buf), buf.numel(), _stream(stream)))
+    return out
+
+
 def render_backward(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, cam,
                     coeff_map: torch.Tensor, codebook: torch.Tensor, grad_features: torch.Tensor,
                     grad_topk_val: Optional[torch.Tensor] = None, grad_codebook: Optional[torch.Tensor] = None,

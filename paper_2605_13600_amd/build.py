@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscoup.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "binning.hip", "uplift.hip", "render.hip", "decode.hip", "backward.hip"]
+SOURCES = ["api.hip", "binning.hip", "uplift.hip", "render.hip", "decode.hip", "backward.hip", "relevancy.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

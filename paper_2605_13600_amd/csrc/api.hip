@@ -610,6 +610,42 @@ scoup_status scoup_decode(const void* coeff_map, scoup_dtype in_dtype, float coe
   return SCOUP_OK;
 }
 
+size_t scoup_relevancy_workspace_bytes(int32_t m_atoms, int32_t n_queries, scoup_dtype in_dtype) {
+  if (m_atoms < 1 || m_atoms > 4096 || n_queries < 1 || n_queries > 1024) return 0;
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3) return 0;
+  return align256(relevancy_frag_bytes(m_atoms, n_queries, in_dtype));
+}
+
+scoup_status scoup_relevancy(const void* coeff, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                             int32_t m_atoms, const float* codebook, int32_t dim, const float* queries,
+                             int32_t n_queries, const float* canon, int32_t n_canon, float temperature,
+                             float* scores, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown input dtype");
+  if (n_pixels < 0) return fail(SCOUP_E_ARG, "n_pixels < 0");
+  if (m_atoms < 1 || m_atoms > 4096) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 4096]");
+  if (dim < 1 || dim > 4096) return fail(SCOUP_E_ARG, "dim must be in [1, 4096]");
+  if (n_queries < 1 || n_queries > 1024) return fail(SCOUP_E_ARG, "n_queries must be in [1, 1024]");
+  if (n_canon < 1 || n_canon > 4) return fail(SCOUP_E_ARG, "n_canon must be in [1, 4]");
+  if (!(temperature > 0.f) || !std::isfinite(temperature)) return fail(SCOUP_E_ARG, "temperature must be > 0");
+  if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
+  if (!codebook || !queries || !canon || !scores || (n_pixels > 0 && !coeff))
+    return fail(SCOUP_E_ARG, "a relevancy array is NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  if (ws_bytes < scoup_relevancy_workspace_bytes(m_atoms, n_queries, in_dtype))
+    return fail(SCOUP_E_WORKSPACE, "relevancy workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  RelevancyArgs a{};
+  a.coeff = coeff; a.P = n_pixels; a.m = m_atoms; a.d = dim; a.in_dtype = in_dtype;
+  a.codebook = codebook; a.queries = queries; a.canon = canon; a.Q = n_queries; a.n_canon = n_canon;
+  a.temperature = temperature; a.out_mul = 1.0f / coeff_scale; a.frag = ws; a.out = scores;
+  HIP_TRY(launch_relevancy(a, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  return SCOUP_OK;
+}
+
 size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t m_atoms,
                                               int32_t dim, int64_t pair_capacity) {
   if (!cam || n_gaussians < 0 || m_atoms < 1 || dim < 1) return 0;

@@ -8,7 +8,7 @@
 namespace scoup {
 
 enum Stage { kStProject = 0, kStScan, kStEmit, kStSortBig, kStComposite, kStTopk, kStRender, kStDecode,
-             kStRenderBwd, kStBwdGemm, kStRowBuild, kNumStages };
+             kStRenderBwd, kStBwdGemm, kStRowBuild, kStRelevancy, kStRelPrep, kNumStages };
 
 // Records a HIP event pair around each launch when stage timing is enabled.
 struct StageTimer {
@@ -120,6 +120,23 @@ size_t decode_codebook_bytes(int m, int d, int in_dtype);
 hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void* out, float* scale,
                                 hipStream_t s, int transposed = 0);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage = kStDecode);
+
+struct RelevancyArgs {
+  const void* coeff;           // [P x m] coefficient map in in_dtype
+  long long P;
+  int m, d, in_dtype;
+  const float* codebook;       // [m x d] float32
+  const float* queries;        // [Q x d] float32
+  const float* canon;          // [n_canon x d] float32
+  int Q, n_canon;
+  float temperature;
+  float out_mul;               // 1 / coefficient scale
+  void* frag;                  // relevancy_frag_bytes(m, Q, in_dtype) of workspace
+  float* out;                  // [P x Q] float32 scores
+};
+int relevancy_groups(int q);
+size_t relevancy_frag_bytes(int m, int q, int in_dtype);
+hipError_t launch_relevancy(const RelevancyArgs& a, hipStream_t s);
 
 struct RenderBwdArgs {
   BinArgs bin;

@@ -310,6 +310,22 @@ def random_unit_vectors(seed: int, n: int, dim: int) -> np.ndarray:
     return q.astype(np.float32)
 
 
+def random_coeff_rows(seed: int, n: int, m_atoms: int, nnz: int = 24, empty_frac: float = 0.1) -> np.ndarray:
+    """(n, M) float32 rows shaped like rendered coefficient maps (Eq. 7):
+    ``nnz`` distinct atoms per row with U(0,1) weights scaled to a row sum
+    1 - T with T ~ U(0,1) (the blend of a few Gaussians' Top-K codes), and a
+    fraction ``empty_frac`` of all-zero background rows."""
+    rng = _streams(seed, 1)[0]
+    nnz = min(nnz, m_atoms)
+    out = np.zeros((n, m_atoms), np.float32)
+    idx = np.argpartition(rng.random((n, m_atoms)), nnz - 1, axis=1)[:, :nnz]
+    v = rng.random((n, nnz))
+    v *= (rng.random(n) / v.sum(axis=1))[:, None]
+    np.put_along_axis(out, idx, v.astype(np.float32), axis=1)
+    out[rng.random(n) < empty_frac] = 0.0
+    return out
+
+
 # ----------------------------------------------------------------------------
 # the five workloads
 # ----------------------------------------------------------------------------

@@ -83,3 +83,32 @@ def test_uplift_argument_validation():
     assert lib.scoup_uplift_accumulate(C.byref(neg), C.byref(v), 256, 0, cap, 1, 256, ws, None, None) == L.E_ARG
     big, keep3 = _views(width=40000)
     assert lib.scoup_uplift_accumulate(C.byref(g), C.byref(big), 256, 0, cap, 1, 256, ws, None, None) == L.E_ARG
+
+
+def test_relevancy_argument_validation():
+    lib = L.load()
+    fake = C.c_void_p(0x1000)          # never dereferenced: every call below fails validation first
+    ws = C.c_void_p(0x10000)
+    args = dict(coeff=fake, dt=L.F32, scale=1.0, P=100, m=64, cb=fake, d=32, q=fake, nq=16, c=fake, nc=4,
+                temp=10.0, out=fake, ws=ws, wsb=1 << 30)
+
+    def call(**kw):
+        a = {**args, **kw}
+        return lib.scoup_relevancy(a["coeff"], a["dt"], a["scale"], a["P"], a["m"], a["cb"], a["d"], a["q"],
+                                   a["nq"], a["c"], a["nc"], a["temp"], a["out"], a["ws"], a["wsb"], None)
+
+    assert call(nc=0) == L.E_ARG and call(nc=5) == L.E_ARG
+    assert call(nq=0) == L.E_ARG and call(nq=1025) == L.E_ARG
+    assert call(temp=0.0) == L.E_ARG and call(temp=float("inf")) == L.E_ARG
+    assert call(m=0) == L.E_ARG and call(d=0) == L.E_ARG and call(dt=7) == L.E_ARG
+    assert call(scale=-1.0) == L.E_ARG and call(P=-1) == L.E_ARG
+    assert call(q=None) == L.E_ARG and call(out=None) == L.E_ARG
+    assert call(ws=C.c_void_p(0x10001)) == L.E_ARG
+    assert call(wsb=16) == L.E_WORKSPACE
+    assert b"workspace" in lib.scoup_last_error()
+    # workspace: one S fragment set per group of 24 queries, two bfloat16 terms for BF16 / FP8 maps
+    b24 = lib.scoup_relevancy_workspace_bytes(256, 24, L.BF16)
+    assert lib.scoup_relevancy_workspace_bytes(256, 25, L.BF16) == 2 * b24
+    assert lib.scoup_relevancy_workspace_bytes(256, 16, L.F32) == 256 * 32 * 4
+    assert b24 == 256 * 32 * 2 * 2
+    assert lib.scoup_relevancy_workspace_bytes(0, 16, L.F32) == 0
