@@ -45,6 +45,34 @@ def flops_per_contribution(k_code: int) -> int:
     return 15 + 2 * k_code
 
 
+def composite_source_hash():
+    """Hash of the compositing kernel's source (its section of uplift.hip and
+    the device header), to tell whether committed counters still apply."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2605_13600_amd", "csrc")
+    up = open(os.path.join(csrc, "uplift.hip")).read()
+    a, b = up.index("constexpr int kEStride"), up.index("// Eq. 6 on one row held by a wave")
+    h = hashlib.sha256(up[a:b].encode())
+    h.update(open(os.path.join(csrc, "scoup_device.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per compositing launch from the committed counter summary
+    (two rocprofv3 passes scaled by a copy of known size), or None when the
+    kernel's source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "composite_scene_1M_200views_hbm_counters.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(": ", 1) for ln in txt.splitlines()
+                if ln.startswith(("source_sha256: ", "traffic_bytes_per_launch: ")))
+    if vals.get("source_sha256") != composite_source_hash():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(sc, rows=192):
     """The FP64 oracle on a bounded sample: all Gaussians, view 0, a band of
     ``rows`` image rows through the centre (projection + compositing +
@@ -318,7 +346,8 @@ def main():
     achieved = per_launch_flops / (comp["avg_us"] * 1e-6) / 1e12
     roofline = dict(kernel="composite", dominant_stage=dom, bound="alu",
                     achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 5), traffic=None,
+                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 5),
+                    traffic=measured_traffic() if sc.views.n_views == 200 and args.workload == "scene" else None,
                     per_launch=f"{nc / sc.views.n_views:.4g} contributions x "
                                f"{flops_per_contribution(sc.views.k_code)} flops")
 

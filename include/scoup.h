@@ -239,7 +239,8 @@ size_t scoup_relevancy_workspace_bytes(int32_t m_atoms, int32_t n_queries, scoup
  *   codebook  device float32 [m_atoms*dim]
  *   queries   device float32 [n_queries*dim]
  *   canon     device float32 [n_canon*dim]
- *   scores    device float32 [n_pixels*n_queries]
+ *   scores    device float32 [n_pixels*n_queries] (coeff and scores may be NULL
+ *             when n_pixels == 0)
  * Requires 1 <= m_atoms <= 4096, 1 <= dim <= 4096, 1 <= n_queries <= 1024,
  * 1 <= n_canon <= 4 and a finite temperature > 0 (else SCOUP_E_ARG).        */
 scoup_status scoup_relevancy(const void* coeff, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,

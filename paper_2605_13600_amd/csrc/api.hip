@@ -39,8 +39,9 @@ int tiles_of(int w, int h, int shift = 4) {
 
 // Workspace layout of one binning pass (+ the uplift's per-view offsets and records).
 struct BinLayout {
-  size_t status, splats, offsets, scan_part, tile_start, big_tiles, radix_hist, tile_ids[2], keys[2], records,
-      total;
+  size_t status, splats, offsets, scan_part, tile_start, big_tiles, bin_hist, radix_hist, tile_ids[2], keys[2],
+      records, total;
+  bool counting;
 };
 
 BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int rec_views) {
@@ -50,10 +51,14 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
   L.status = off; off = align256(off + sizeof(Status));
   L.splats = off; off = align256(off + sizeof(GSplat) * nn);
   L.offsets = off; off = align256(off + 4 * (size_t)(n + 1) * (size_t)off_views);
-  const long long sparts = std::max(scan_blocks(n), scan_blocks(128 * radix_blocks(cap)));
+  const long long sparts =
+      std::max(std::max(scan_blocks(n), scan_blocks(128 * radix_blocks(cap))), scan_blocks(max_tiles));
   L.scan_part = off; off = align256(off + 8 * (size_t)std::max<long long>(1, sparts));
   L.tile_start = off; off = align256(off + 4 * (size_t)(max_tiles + 1));
   L.big_tiles = off; off = align256(off + 4 * (size_t)max_tiles);
+  L.counting = count_binning_ok(n, max_tiles);
+  L.bin_hist = off;
+  if (L.counting) off = align256(off + 4 * (size_t)count_groups(n) * (size_t)max_tiles);
   L.radix_hist = off; off = align256(off + 4 * 128 * (size_t)std::max<long long>(1, radix_blocks(cap)));
   L.tile_ids[0] = off; off = align256(off + 4 * (size_t)cap);
   L.tile_ids[1] = off; off = align256(off + 4 * (size_t)cap);
@@ -90,6 +95,7 @@ void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const BinLayout&
   b.scan_part = reinterpret_cast<unsigned long long*>(base + L.scan_part);
   b.tile_start = reinterpret_cast<unsigned int*>(base + L.tile_start);
   b.big_tiles = reinterpret_cast<unsigned int*>(base + L.big_tiles);
+  b.bin_hist = L.counting ? reinterpret_cast<unsigned int*>(base + L.bin_hist) : nullptr;
   b.radix_hist = reinterpret_cast<unsigned int*>(base + L.radix_hist);
   for (int k = 0; k < 2; ++k) {
     b.tile_ids[k] = reinterpret_cast<unsigned int*>(base + L.tile_ids[k]);
@@ -107,6 +113,7 @@ hipError_t ensure_lds_limits() {
     g_lds_err = render_set_lds_limits();
     if (g_lds_err == hipSuccess) g_lds_err = decode_set_lds_limits();
     if (g_lds_err == hipSuccess) g_lds_err = render_bwd_set_lds_limits();
+    if (g_lds_err == hipSuccess) g_lds_err = binning_set_lds_limits();
   });
   return g_lds_err;
 }
@@ -287,6 +294,7 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
     return fail(SCOUP_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
                                        std::to_string(L.total) + " this capacity and view batch need");
   }
+  HIP_TRY(ensure_lds_limits());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   Status* status = reinterpret_cast<Status*>(base + L.status);
@@ -297,7 +305,7 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
 
   UpliftViewArgs a{};
   BinArgs& b = a.bin;
-  fill_bin(b, g, base, L, pair_capacity, 3, 2048);
+  fill_bin(b, g, base, L, pair_capacity, 3, kSortCap);
   a.n_levels = n_levels;
   a.m_atoms = v->m_atoms;
   unsigned int* off_all = b.offsets;
@@ -427,6 +435,7 @@ scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, 
     g_required_pairs = pair_capacity;
     return fail(SCOUP_E_WORKSPACE, "workspace too small for this capacity and view batch");
   }
+  HIP_TRY(ensure_lds_limits());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* fbase = static_cast<char*>(ws);
   float* F = reinterpret_cast<float*>(fbase);
@@ -440,7 +449,7 @@ scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, 
   HIP_TRY(launch_region_features(v->code_idx, v->code_val, rt, v->k_code, codebook, v->m_atoms, dim, F, status, s));
   UpliftViewArgs a{};
   BinArgs& b = a.bin;
-  fill_bin(b, g, base, L, pair_capacity, 3, 2048);
+  fill_bin(b, g, base, L, pair_capacity, 3, kSortCap);
   a.n_levels = 1;
   a.m_atoms = v->m_atoms;
   unsigned int* off_all = b.offsets;
@@ -547,9 +556,7 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   RenderViewArgs a{};
-  fill_bin(a.bin, g, base, L, capacity, shift, 0);
-  const int sort_cap = [&] { int c = 1; while (2 * c <= 32 * (m_atoms + 1)) c *= 2; return c; }();
-  a.bin.sort_cap = sort_cap;
+  fill_bin(a.bin, g, base, L, capacity, shift, kSortCap);
   a.bin.cam = to_dev(*cam);
   a.bin.tiles_x = (cam->width + 7) / 8;
   a.bin.n_tiles = mt;
@@ -630,7 +637,7 @@ scoup_status scoup_relevancy(const void* coeff, scoup_dtype in_dtype, float coef
   if (n_canon < 1 || n_canon > 4) return fail(SCOUP_E_ARG, "n_canon must be in [1, 4]");
   if (!(temperature > 0.f) || !std::isfinite(temperature)) return fail(SCOUP_E_ARG, "temperature must be > 0");
   if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
-  if (!codebook || !queries || !canon || !scores || (n_pixels > 0 && !coeff))
+  if (!codebook || !queries || !canon || (n_pixels > 0 && (!coeff || !scores)))
     return fail(SCOUP_E_ARG, "a relevancy array is NULL");
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
   if (ws_bytes < scoup_relevancy_workspace_bytes(m_atoms, n_queries, in_dtype))
@@ -698,10 +705,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   HIP_TRY(launch_decode(d, s, kStBwdGemm));
   HIP_TRY(launch_gemm_at_b(coeff_map, grad_features, P, m_atoms, dim, grad_codebook, s));
   RenderBwdArgs a{};
-  fill_bin(a.bin, g, bbase, L, capacity, shift, 0);
-  int sort_cap = 1;
-  while (2 * sort_cap <= 32 * (m_atoms + 1)) sort_cap *= 2;
-  a.bin.sort_cap = sort_cap;
+  fill_bin(a.bin, g, bbase, L, capacity, shift, kSortCap);
   a.bin.cam = to_dev(*cam);
   a.bin.tiles_x = (cam->width + 7) / 8;
   a.bin.n_tiles = mt;

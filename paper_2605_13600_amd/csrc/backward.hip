@@ -20,10 +20,10 @@ constexpr int kBwdKMax = 16;
 // LDS, reduce over the block's pixels and add to grad_val.
 __global__ __launch_bounds__(64) void k_render_bwd(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
-    unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
-    const int* __restrict__ topk_idx, int K, int M, int sort_cap, const float* __restrict__ dW,
+    const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
+    const int* __restrict__ topk_idx, int K, int M, const float* __restrict__ dW,
     float* __restrict__ grad_val, Status* st) {
-  extern __shared__ float rows[];          // 64 * (M+1) floats; aliased by the sort keys first
+  extern __shared__ float rows[];          // 64 * (M+1) floats
   __shared__ unsigned int s_id[64];
   __shared__ int s_ti[64 * kBwdKMax];
   if (st->view_overflow) return;
@@ -39,16 +39,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const bool inside = px < W && py < H;
   const int stride = M + 1;
 
-  if (L <= sort_cap) {
-    unsigned long long* sk = reinterpret_cast<unsigned long long*>(rows);
-    int n2 = 1;
-    while (n2 < L) n2 <<= 1;
-    for (int j = lane; j < n2; j += 64) sk[j] = j < L ? keys[start + j] : ~0ull;
-    __syncthreads();
-    bitonic_lds(sk, n2, lane, 64);
-    for (int j = lane; j < L; j += 64) keys[start + j] = sk[j];
-    __syncthreads();
-  }
   for (int p = 0; p < 64; ++p) {
     const int ox = tile_x0 + (p & 7), oy = tile_y0 + (p >> 3);
     const bool in = ox < W && oy < H;
@@ -166,7 +156,7 @@ hipError_t launch_render_bwd_view(RenderBwdArgs& a, hipStream_t s) {
   const size_t lds = sizeof(float) * 64 * (size_t)(a.m_atoms + 1);
   StageTimer::begin(kStRenderBwd, s);
   hipLaunchKernelGGL(k_render_bwd, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start, b.keys[b.sorted],
-                     b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.k, a.m_atoms, b.sort_cap, a.dW,
+                     b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.k, a.m_atoms, a.dW,
                      a.grad_val, b.status);
   StageTimer::end(kStRenderBwd, s);
   return hipGetLastError();

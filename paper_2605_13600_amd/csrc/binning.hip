@@ -1,24 +1,32 @@
 // Projection and tile binning shared by the uplift, the render and the
 // backward (Sec. 3: the 3DGS tile rasterizer whose blending weights feed
-// Eq. 1-2; Eq. 1's "ordered from front to back").  No global atomics:
+// Eq. 1-2; Eq. 1's "ordered from front to back"):
 //
 //   k_project     one thread per Gaussian: FP64 EWA projection -> GSplat,
 //                 number of overlapped tiles n_i
 //   scan          device-wide exclusive scan of n_i -> Gaussian-major pair
 //                 offsets off_i (also the record slots of the uplift)
-//   k_emit        pair (i, t) at off_i + (row-major index of t in i's rect):
-//                 tile id + key (float32 depth bits << 32 | i)
-//   radix         stable LSD radix sort of the pairs by tile id (7-bit digits)
-//   k_tile_ranges tile t owns sorted pairs [tile_start[t], tile_start[t+1])
-//   k_sort_big    tiles longer than the consumer's LDS sort are sorted by
-//                 (depth, id) here; shorter ones are sorted in LDS by the consumer
+//   k_bin_count / k_bin_colscan / tile scan / k_bin_place
+//                 pairs grouped by tile in one counting pass: key (float32
+//                 depth bits << 32 | i) of pair (i, t) placed in t's list,
+//                 tile t owns [tile_start[t], tile_start[t+1])
+//   (larger images: k_emit + stable LSD radix sort by tile id + k_tile_ranges)
+//   k_sort_blocks each block list of at most kSortCap pairs sorted by (depth,
+//                 id) in LDS, one workgroup per block
+//   k_sort_big    lists longer than kSortCap sorted in global memory
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 
 #include "scoup_device.h"
 #include "scoup_internal.h"
 
 namespace scoup {
+
+constexpr int kCountThreads = 512;
+constexpr int kCountGroups = 256;          // workgroups of the counting pass (at least)
+constexpr int kCountMaxTiles = 49152;      // 16-bit LDS counters: 96 KB
 
 // ---------------------------------------------------------------------------
 // projection (one thread per Gaussian), FP64 arithmetic, FP32 storage
@@ -251,7 +259,126 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
 }
 
 // ---------------------------------------------------------------------------
+// Grouping by tile with one counting pass (images up to kCountMaxTiles
+// tiles).  Workgroup w owns a contiguous range of Gaussians and counts its
+// pairs per tile in LDS (two 16-bit counters per word); a column scan over
+// the workgroups and a scan over tiles give every (workgroup, tile) its base;
+// the placing pass re-walks the Gaussians and drops each key at base + a
+// local LDS ticket.  The order inside a (workgroup, tile) run follows the
+// tickets; the per-block sort by (depth, id) that follows makes the result
+// independent of it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __restrict__ splats, long long n,
+                                                             int tiles_x, int n_tiles, int tile_shift,
+                                                             long long per_wg, unsigned int* __restrict__ hist,
+                                                             const Status* st) {
+  extern __shared__ unsigned int h[];                // ceil(n_tiles / 2) words
+  if (st->view_overflow) return;
+  const int nw = (n_tiles + 1) >> 1;
+  for (int j = threadIdx.x; j < nw; j += kCountThreads) h[j] = 0u;
+  __syncthreads();
+  const long long i0 = (long long)blockIdx.x * per_wg;
+  const long long i1 = min(n, i0 + per_wg);
+  for (long long i = i0 + threadIdx.x; i < i1; i += kCountThreads) {
+    const GSplat g = splats[i];
+    if (g.bx0 > g.bx1) continue;
+    const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
+    const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const int t = ty * tiles_x + tx;
+        atomicAdd(&h[t >> 1], 1u << (16 * (t & 1)));
+      }
+  }
+  __syncthreads();
+  unsigned int* row = hist + (long long)blockIdx.x * n_tiles;
+  for (int t = threadIdx.x; t < n_tiles; t += kCountThreads) row[t] = (h[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
+}
+
+// hist[w][t] <- sum of hist[w'][t] over w' < w; tile_len[t] <- sum over all w
+__global__ __launch_bounds__(256) void k_bin_colscan(unsigned int* __restrict__ hist, int n_wg, int n_tiles,
+                                                     unsigned int* __restrict__ tile_len, const Status* st) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  if (st->view_overflow) { tile_len[t] = 0u; return; }     // empty lists; the view is retried
+  unsigned int run = 0u;
+  int w = 0;
+  for (; w + 8 <= n_wg; w += 8) {
+    unsigned int v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = hist[(long long)(w + k) * n_tiles + t];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      hist[(long long)(w + k) * n_tiles + t] = run;
+      run += v[k];
+    }
+  }
+  for (; w < n_wg; ++w) {
+    const unsigned int v = hist[(long long)w * n_tiles + t];
+    hist[(long long)w * n_tiles + t] = run;
+    run += v;
+  }
+  tile_len[t] = run;
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __restrict__ splats, long long n,
+                                                             int tiles_x, int n_tiles, int tile_shift,
+                                                             long long per_wg, const unsigned int* __restrict__ hist,
+                                                             const unsigned int* __restrict__ tile_start,
+                                                             unsigned long long* __restrict__ keys,
+                                                             const Status* st) {
+  extern __shared__ unsigned int h[];
+  if (st->view_overflow) return;
+  const int nw = (n_tiles + 1) >> 1;
+  for (int j = threadIdx.x; j < nw; j += kCountThreads) h[j] = 0u;
+  __syncthreads();
+  const unsigned int* base = hist + (long long)blockIdx.x * n_tiles;
+  const long long i0 = (long long)blockIdx.x * per_wg;
+  const long long i1 = min(n, i0 + per_wg);
+  for (long long i = i0 + threadIdx.x; i < i1; i += kCountThreads) {
+    const GSplat g = splats[i];
+    if (g.bx0 > g.bx1) continue;
+    const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
+    const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
+    const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const int t = ty * tiles_x + tx;
+        const unsigned int sh = 16 * (t & 1);
+        const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        keys[tile_start[t] + base[t] + ticket] = key;
+      }
+  }
+}
+
+// tiles longer than sort_cap go to k_sort_big
+__global__ __launch_bounds__(256) void k_bin_big(const unsigned int* __restrict__ tile_start, int n_tiles,
+                                                 int sort_cap, unsigned int* __restrict__ big_tiles, Status* st) {
+  if (st->view_overflow) return;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  if (tile_start[t + 1] - tile_start[t] > (unsigned int)sort_cap) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
+}
+
+hipError_t binning_set_lds_limits() {
+  const int bytes = (int)sizeof(unsigned int) * (kCountMaxTiles / 2);
+  hipError_t e = hipFuncSetAttribute((const void*)k_bin_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+int count_groups(long long n) {
+  const long long need = (n + 65534) / 65535;              // at most 65535 Gaussians per 16-bit counter
+  return (int)std::max<long long>(kCountGroups, need);
+}
+
+bool count_binning_ok(long long n, int n_tiles) {
+  return n_tiles <= kCountMaxTiles && count_groups(n) <= 4 * kCountGroups;
+}
+
+// ---------------------------------------------------------------------------
 // stable LSD radix sort of (tile id, key) pairs by tile id, 7-bit digits
+// (larger images)
 // ---------------------------------------------------------------------------
 constexpr int kRadixBits = 7;
 constexpr int kRadixBins = 1 << kRadixBits;
@@ -388,6 +515,27 @@ __global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restric
   }
 }
 
+// Depth order inside every block list of lo < L <= hi pairs: one workgroup of
+// NT threads per block, bitonic network over the list in LDS (ascending
+// (depth, id)).  Short lists (the common case) run in one-wave workgroups
+// with a small static LDS buffer, so many blocks sort concurrently per CU.
+template <int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_sort_blocks(unsigned long long* __restrict__ keys,
+                                                    const unsigned int* __restrict__ tile_start, int lo,
+                                                    const Status* st) {
+  __shared__ unsigned long long sk[CAP];
+  if (st->view_overflow) return;
+  const unsigned int start = tile_start[blockIdx.x];
+  const int L = (int)(tile_start[blockIdx.x + 1] - start);
+  if (L <= lo || L > CAP) return;
+  int n2 = 1;
+  while (n2 < L) n2 <<= 1;
+  for (int j = threadIdx.x; j < n2; j += NT) sk[j] = j < L ? keys[start + j] : ~0ull;
+  __syncthreads();
+  bitonic_lds(sk, n2, threadIdx.x, NT);
+  for (int j = threadIdx.x; j < L; j += NT) keys[start + j] = sk[j];
+}
+
 int radix_passes(int n_tiles) {
   int bits = 1;
   while ((1 << bits) < n_tiles) ++bits;
@@ -396,6 +544,18 @@ int radix_passes(int n_tiles) {
 
 long long radix_blocks(long long capacity) { return (capacity + kRadixBlock - 1) / kRadixBlock; }
 long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+// depth order inside every tile list of the sorted buffer
+static void sort_lists(const BinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
+                     a.status);
+  if (a.n_tiles > 0) {            // lists of 2..512 and 513..kSortCap pairs
+    hipLaunchKernelGGL((k_sort_blocks<64, 512>), dim3(a.n_tiles), dim3(64), 0, s, a.keys[a.sorted], a.tile_start,
+                       1, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<256, kSortCap>), dim3(a.n_tiles), dim3(256), 0, s, a.keys[a.sorted],
+                       a.tile_start, 512, a.status);
+  }
+}
 
 hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   const int nb = (int)((a.n + 255) / 256);
@@ -414,14 +574,38 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   if (sb > 0)
     hipLaunchKernelGGL(k_scan_down, dim3(sb), dim3(256), 0, s, a.offsets, a.n, a.scan_part, a.offsets + a.n);
   StageTimer::end(kStScan, s);
-  if (a.n > 0) {
+  const bool counting = a.bin_hist && count_binning_ok(a.n, a.n_tiles);
+  if (a.n > 0 && !counting) {
     StageTimer::begin(kStEmit, s);
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_shift, a.offsets,
                        a.tile_ids[0], a.keys[0], a.status);
     StageTimer::end(kStEmit, s);
   }
-  // radix sort by tile id: passes alternate between the two buffers
   StageTimer::begin(kStSortBig, s);
+  if (counting) {
+    const int nwg = count_groups(a.n);
+    const long long per_wg = std::max<long long>(1, (a.n + nwg - 1) / nwg);
+    const size_t lds = sizeof(unsigned int) * (size_t)((a.n_tiles + 1) / 2);
+    hipLaunchKernelGGL(k_bin_count, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
+                       a.tile_shift, per_wg, a.bin_hist, a.status);
+    hipLaunchKernelGGL(k_bin_colscan, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.bin_hist, nwg, a.n_tiles,
+                       a.tile_start, a.status);
+    const int tsb = (int)scan_blocks(a.n_tiles);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.scan_part, tsb, 0ull, (Status*)nullptr);
+    hipLaunchKernelGGL(k_scan_down, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part,
+                       a.tile_start + a.n_tiles);
+    hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
+                       a.tile_shift, per_wg, (const unsigned int*)a.bin_hist, (const unsigned int*)a.tile_start,
+                       a.keys[0], a.status);
+    hipLaunchKernelGGL(k_bin_big, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.tile_start, a.n_tiles,
+                       a.sort_cap, a.big_tiles, a.status);
+    a.sorted = 0;
+    sort_lists(a, s);
+    StageTimer::end(kStSortBig, s);
+    return hipGetLastError();
+  }
+  // radix sort by tile id: passes alternate between the two buffers
   const int passes = radix_passes(a.n_tiles);
   const int rb = (int)radix_blocks(a.capacity);
   const long long hlen = (long long)rb * kRadixBins;
@@ -442,8 +626,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   a.sorted = cur;
   hipLaunchKernelGGL(k_tile_ranges, dim3((a.n_tiles + 1 + 255) / 256), dim3(256), 0, s, a.tile_ids[cur],
                      a.n_tiles, a.tile_start, a.sort_cap, a.big_tiles, a.status);
-  hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[cur], a.tile_start, a.big_tiles,
-                     a.status);
+  sort_lists(a, s);
   StageTimer::end(kStSortBig, s);
   return hipGetLastError();
 }

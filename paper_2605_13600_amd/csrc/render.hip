@@ -1,6 +1,7 @@
 // Sparse coefficient render (Eq. 7): W_hat_v(p) = sum_{i in N_{v,p}} w_hat_i e_i(v,p)
 // over K (atom, value) pairs per Gaussian, front-to-back weights e from Eq. 2.
-// gfx950, wave64: one 8x8 pixel block per workgroup (one wave); every pixel
+// gfx950, wave64: one 8x8 pixel block per workgroup (one wave), its list in
+// depth order (binning); every pixel
 // keeps its dense M-wide coefficient row in LDS (stride M+1 to spread banks),
 // accumulates in float32 and writes the row once, converted to the output type.
 #include <hip/hip_runtime.h>
@@ -19,11 +20,10 @@ __device__ __forceinline__ void store_out(uint8_t* p, float v) { *p = f32_to_e4m
 template <typename OutT>
 __global__ __launch_bounds__(64) void k_render_coeff(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
-    unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
+    const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
     const int* __restrict__ topk_idx, const float* __restrict__ topk_val, int K, int M,
-    int sort_cap, OutT* __restrict__ out, float out_scale, float* __restrict__ t_final,
-    Status* st) {
-  extern __shared__ float rows[];          // 64 * (M+1) floats; aliased by the sort keys first
+    OutT* __restrict__ out, float out_scale, float* __restrict__ t_final, Status* st) {
+  extern __shared__ float rows[];          // 64 * (M+1) floats
   __shared__ int s_ti[64 * kRenderKMax];
   __shared__ float s_tv[64 * kRenderKMax];
   if (st->view_overflow) return;
@@ -37,16 +37,6 @@ __global__ __launch_bounds__(64) void k_render_coeff(
   const bool inside = px < W && py < H;
   const int stride = M + 1;
 
-  if (L > 0 && L <= sort_cap) {            // depth order of the block's list, in LDS
-    unsigned long long* sk = reinterpret_cast<unsigned long long*>(rows);
-    int n2 = 1;
-    while (n2 < L) n2 <<= 1;
-    for (int j = lane; j < n2; j += 64) sk[j] = j < L ? keys[start + j] : ~0ull;
-    __syncthreads();
-    bitonic_lds(sk, n2, lane, 64);
-    for (int j = lane; j < L; j += 64) keys[start + j] = sk[j];
-    __syncthreads();
-  }
   for (int j = lane; j < 64 * stride; j += 64) rows[j] = 0.0f;
   __syncthreads();
 
@@ -125,18 +115,18 @@ hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
     case SCOUP_F32:
       hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start,
                          b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
-                         a.m_atoms, b.sort_cap, (float*)a.out, a.out_scale, a.t_final, b.status);
+                         a.m_atoms, (float*)a.out, a.out_scale, a.t_final, b.status);
       break;
     case SCOUP_BF16:
       hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
                          b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
-                         a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint16_t*)a.out, a.out_scale,
+                         a.topk_val, a.k, a.m_atoms, (uint16_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;
     default:
       hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
                          b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
-                         a.topk_val, a.k, a.m_atoms, b.sort_cap, (uint8_t*)a.out, a.out_scale,
+                         a.topk_val, a.k, a.m_atoms, (uint8_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;
   }
@@ -145,7 +135,7 @@ hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
 }
 
 hipError_t render_set_lds_limits() {
-  const int bytes = 160 * 1024 - (int)(sizeof(GSplat) * 64 + 8 * 64 * kRenderKMax) - 1024;
+  const int bytes = 160 * 1024 - (int)(8 * 64 * kRenderKMax) - 1024;
   hipError_t e = hipFuncSetAttribute((const void*)k_render_coeff<float>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;

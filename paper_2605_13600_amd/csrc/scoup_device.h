@@ -10,7 +10,7 @@ namespace scoup {
 
 constexpr int kTile = 16;            // screen tile edge (pixels); 4 waves of 8x8 per tile
 constexpr int kTileThreads = 256;
-constexpr int kSortCap = 4096;       // tile lists up to this length are sorted in LDS
+constexpr int kSortCap = 4096;       // block lists up to this length are sorted in LDS (k_sort_blocks)
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;

@@ -37,6 +37,7 @@ struct BinArgs {
   unsigned int* radix_hist;        // [128 * radix blocks]
   unsigned int* tile_start;        // [n_tiles + 1]
   unsigned int* big_tiles;         // [n_tiles] tiles longer than sort_cap
+  unsigned int* bin_hist;          // [count_groups(n) x n_tiles] counting-pass bases, or NULL (radix path)
   long long capacity;
   Status* status;
   int sorted;              // set by launch_bin_view: which buffer holds the sorted pairs
@@ -46,6 +47,9 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s);
 int radix_passes(int n_tiles);
 long long radix_blocks(long long capacity);
 long long scan_blocks(long long n);
+int count_groups(long long n);
+hipError_t binning_set_lds_limits();
+bool count_binning_ok(long long n, int n_tiles);
 
 // One view of the uplift: composite + per-(Gaussian, block) region records,
 // for up to kMaxLevels region maps (semantic levels) sharing one compositing.

@@ -27,16 +27,20 @@ namespace scoup {
 
 // ---------------------------------------------------------------------------
 // composite + per-(Gaussian, block, region) reduction: one 8x8 pixel block per
-// workgroup (one wave), lane l = pixel (l & 7, l >> 3) of the block.
-// Per batch of 64 depth-sorted Gaussians the wave writes every lane's weight
-// e into an LDS matrix E[Gaussian][pixel]; afterwards lane k sums row k over
-// the pixels of the block's two record regions (a transposed reduction: no
-// cross-lane traffic inside the sequential compositing loop) and writes the
-// pair's two records.  Pixels of a third or further region in the block
-// (rare) are reduced across the wave and added to the accumulator directly.
+// workgroup (one wave), lane l = pixel (l & 7, l >> 3) of the block, the
+// block's list already in depth order (binning).
+// Per batch of B depth-ordered Gaussians the wave writes every lane's weight
+// e into an LDS matrix E[Gaussian][pixel]; afterwards lane g B + k sums row k
+// over the pixels [g B, g B + B) of the block's two record regions (a
+// transposed reduction: no cross-lane traffic inside the sequential
+// compositing loop), the 64 / B partial sums are combined across lane groups
+// and the pair's two records are written.  Pixels of a third or further
+// region in the block (rare) are reduced across the wave and added to the
+// accumulator directly.  B trades LDS (B x 65 floats, which sets occupancy)
+// against the per-batch overhead.
 // ---------------------------------------------------------------------------
-constexpr int kBlkSortCap = 2048;
 constexpr int kEStride = 65;
+constexpr int kCompositeBatch = 32;
 
 struct LevelSlots {           // per level, per lane
   int reg, slot;
@@ -45,11 +49,13 @@ struct LevelSlots {           // per level, per lane
   float rg0, rg1;
 };
 
+template <int B>
 __global__ __launch_bounds__(64) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
-    unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
+    const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
-  __shared__ float smem[64 * kEStride];       // sort keys (2048 x 8 B) first, then E
+  static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
+  __shared__ float E[B * kEStride];
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -87,17 +93,6 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   }
   if (L == 0) return;
 
-  if (L <= kBlkSortCap) {        // depth order in LDS, written back for the batches
-    unsigned long long* sk = reinterpret_cast<unsigned long long*>(smem);
-    int n2 = 1;
-    while (n2 < L) n2 <<= 1;
-    for (int j = lane; j < n2; j += 64) sk[j] = j < L ? keys[start + j] : ~0ull;
-    __syncthreads();
-    bitonic_lds(sk, n2, lane, 64);
-    for (int j = lane; j < L; j += 64) keys[start + j] = sk[j];
-    __syncthreads();
-  }
-  float* E = smem;
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = 1.0f;
   bool done = !inside;
@@ -106,14 +101,16 @@ __global__ __launch_bounds__(64) void k_composite_blk(
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l)
     if (l < n_levels) any_has2 = any_has2 || ls[l].has2;
-  for (int b0 = 0; b0 < L; b0 += 64) {
+  const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
+  const int gq0 = lane - gk;                   // first pixel of the lane's group
+  for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(!done) == 0ull;
-    const int j = b0 + lane;
-    const int nb = min(64, L - b0);
+    const int j = b0 + gk;
+    const int nb = min(B, L - b0);
     SplatLane mine;
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
-    if (j < L) {
+    if (j < L) {                               // every lane group holds the batch's splats
       my_id = (unsigned int)keys[start + j];
       const GSplat gg = splats[my_id];
       mine.load(gg);
@@ -181,24 +178,30 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       }
     }
     __syncthreads();
-    if (lane < nb) {   // every pair's two record slots per level are written, zero weight included
-      const bool had = (contributed >> lane) & 1ull;
-      const float* row = E + lane * kEStride;
-      const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
-      const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+    // every pair's two record slots per level are written, zero weight included
+    const bool had = gk < nb && ((contributed >> gk) & 1ull);
+    const float* row = E + gk * kEStride + gq0;
+    const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
 #pragma unroll
-      for (int l = 0; l < kMaxLevels; ++l) {
-        if (l >= n_levels) break;
-        float w0 = 0.0f, w1 = 0.0f;
-        if (had) {
-          const unsigned long long m0 = ls[l].mask0, m1 = ls[l].mask1;
+    for (int l = 0; l < kMaxLevels; ++l) {
+      if (l >= n_levels) break;
+      float w0 = 0.0f, w1 = 0.0f;
+      if (had) {
+        const unsigned long long m0 = ls[l].mask0 >> gq0, m1 = ls[l].mask1 >> gq0;
 #pragma unroll 8
-          for (int q = 0; q < 64; ++q) {
-            const float x = row[q];
-            if ((m0 >> q) & 1ull) w0 += x;
-            else if ((m1 >> q) & 1ull) w1 += x;
-          }
+        for (int q = 0; q < B; ++q) {
+          const float x = row[q];
+          if ((m0 >> q) & 1ull) w0 += x;
+          else if ((m1 >> q) & 1ull) w1 += x;
         }
+      }
+#pragma unroll
+      for (int o = B; o < 64; o <<= 1) {       // combine the lane groups
+        w0 += __shfl_xor(w0, o, 64);
+        w1 += __shfl_xor(w1, o, 64);
+      }
+      if (lane < nb) {
+        const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
         float2* rec = args.lv[l].records;
         rec[2ull * p] = make_float2(ls[l].rg0, w0);
         rec[2ull * p + 1] = make_float2(ls[l].rg1, w1);
@@ -261,10 +264,12 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 }
 
 // ---------------------------------------------------------------------------
-// row build: G <= 64 consecutive Gaussians per workgroup, lane g of every wave
-// owns Gaussian i0 + g, wave w walks views w, w+4, ...; rows (stride M+1) in
-// LDS take the code of each record with LDS atomic adds; no barriers between
-// views.  Rows are written back coalesced, Top-K read from LDS.
+// row build: G (a power of two <= 16) consecutive Gaussians per workgroup;
+// lane l of wave w owns Gaussian i0 + l % G and walks views
+// w (64/G) + l / G, stepping by 4 (64/G), so 64/G views per wave are in flight;
+// rows (stride M+1) in LDS take the code of each record with LDS atomic adds;
+// no barriers between views.  Rows are written back coalesced, Top-K and
+// entropy read from LDS.
 // ---------------------------------------------------------------------------
 template <int NS>
 __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
@@ -273,14 +278,16 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   const long long i0 = (long long)blockIdx.x * G;
   const int gn = (int)min((long long)G, a.n - i0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int VL = 64 / G;                     // views per wave in flight
+  const int g = lane % G, vsub = lane / G;
   float* acc = a.acc + i0 * M;
   for (int j = tid; j < gn * M; j += 256) rows[(j / M) * stride + (j % M)] = acc[j];
   __syncthreads();
   const unsigned int cap = (unsigned int)a.capacity;
-  if (lane < gn) {
-    float* row = rows + lane * stride;
-    for (int v = wave; v < a.n_views; v += 4) {
-      const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0 + lane;
+  if (g < gn) {
+    float* row = rows + g * stride;
+    for (int v = wave * VL + vsub; v < a.n_views; v += 4 * VL) {
+      const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0 + g;
       const unsigned int lo = min(offv[0], cap), hi = min(offv[1], cap);
       const float2* recv = a.records + (long long)v * 2 * a.capacity;
       for (unsigned int r = 2 * lo; r < 2 * hi; ++r) {
@@ -443,14 +450,21 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
+  hipLaunchKernelGGL(k_composite_blk<kCompositeBatch>, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
   StageTimer::end(kStComposite, s);
   return hipGetLastError();
 }
 
-int rowbuild_group(int m) { return std::max(1, std::min(64, 16384 / (m + 1))); }
+// Gaussians per row-build workgroup: a power of two (lanes split into
+// Gaussians x views), rows within 64 KB of LDS, at most 16 so that four or
+// more views per wave are in flight
+int rowbuild_group(int m) {
+  int g = 16;
+  while (g > 1 && g * (m + 1) > 16384) g >>= 1;
+  return g;
+}
 
 hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;

@@ -102,7 +102,7 @@ def test_relevancy_argument_validation():
     assert call(temp=0.0) == L.E_ARG and call(temp=float("inf")) == L.E_ARG
     assert call(m=0) == L.E_ARG and call(d=0) == L.E_ARG and call(dt=7) == L.E_ARG
     assert call(scale=-1.0) == L.E_ARG and call(P=-1) == L.E_ARG
-    assert call(q=None) == L.E_ARG and call(out=None) == L.E_ARG
+    assert call(q=None) == L.E_ARG and call(out=None) == L.E_ARG and call(c=None) == L.E_ARG
     assert call(ws=C.c_void_p(0x10001)) == L.E_ARG
     assert call(wsb=16) == L.E_WORKSPACE
     assert b"workspace" in lib.scoup_last_error()
