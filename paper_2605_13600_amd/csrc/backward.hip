@@ -54,26 +54,25 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   for (int b0 = 0; b0 < L; b0 += 64) {
     if (__ballot(!done) == 0ull) break;
     const int j = b0 + lane;
-    SplatLane mine;
+    BlockSplat mine;
     if (j < L) {
       const unsigned int id = (unsigned int)keys[start + j];
-      mine.load(splats[id]);
+      mine.load(splats[id], tile_x0, tile_y0);
       s_id[lane] = id;
       for (int k = 0; k < K; ++k) s_ti[lane * K + k] = topk_idx[(long long)id * K + k];
     }
     __syncthreads();
     const int nb = min(64, L - b0);
     for (int k = 0; k < nb; ++k) {
-      const SplatLane g = mine.bcast(k);
-      const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
-      const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
+      const BlockSplat g = mine.bcast(k);
+      const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
       const float q = fmaf(u, u, v * v);
-      const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
-      const bool take = !done && alpha >= kAlphaMin;
+      const bool take = !done && q <= g.qmax;
       if (__ballot(take) == 0ull) continue;
       float e = 0.0f;
       if (take) {
+        const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
         const float testT = T * (1.0f - alpha);
         if (testT < kTMin) {
           done = true;

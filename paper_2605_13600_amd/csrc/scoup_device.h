@@ -36,23 +36,25 @@ static_assert(sizeof(GSplat) == 48, "GSplat layout");
 // The fields of a GSplat that compositing needs, held by the lane that loaded
 // it; bcast(k) reads lane k's copy into every lane via SGPRs (v_readlane), so
 // the sequential per-Gaussian loop does not wait on LDS.
-struct SplatLane {
-  int ix, iy;
-  float fx, fy, l00, l10, l11, opacity;
-  __device__ __forceinline__ void load(const GSplat& g) {
-    ix = g.ix; iy = g.iy; fx = g.fx; fy = g.fy; l00 = g.l00; l10 = g.l10; l11 = g.l11; opacity = g.opacity;
+// One batch Gaussian held by its lane, in block-relative form for the
+// compositing loop: integer centre offset from the block origin (exact in
+// float32), fraction, scaled conic factor, opacity and the largest q that
+// still gives alpha >= 1/255 (alpha = o 2^-q >= 1/255  <=>  q <= log2(255 o)).
+struct BlockSplat {
+  float hx, hy, fx, fy, l00, l10, l11, opacity, qmax;
+  __device__ __forceinline__ void load(const GSplat& g, int x0, int y0) {
+    hx = (float)(g.ix - x0); hy = (float)(g.iy - y0);
+    fx = g.fx; fy = g.fy; l00 = g.l00; l10 = g.l10; l11 = g.l11; opacity = g.opacity;
+    qmax = g.opacity > 0.0f ? log2f(255.0f * g.opacity) : -1.0f;
   }
-  __device__ __forceinline__ SplatLane bcast(int k) const {
-    SplatLane r;
-    r.ix = __builtin_amdgcn_readlane(ix, k);
-    r.iy = __builtin_amdgcn_readlane(iy, k);
-    r.fx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fx), k));
-    r.fy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fy), k));
-    r.l00 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l00), k));
-    r.l10 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l10), k));
-    r.l11 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l11), k));
-    r.opacity = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(opacity), k));
+  __device__ __forceinline__ BlockSplat bcast(int k) const {
+    BlockSplat r;
+    r.hx = rl(hx, k); r.hy = rl(hy, k); r.fx = rl(fx, k); r.fy = rl(fy, k);
+    r.l00 = rl(l00, k); r.l10 = rl(l10, k); r.l11 = rl(l11, k); r.opacity = rl(opacity, k); r.qmax = rl(qmax, k);
     return r;
+  }
+  static __device__ __forceinline__ float rl(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
   }
 };
 

@@ -42,13 +42,6 @@ namespace scoup {
 constexpr int kEStride = 65;
 constexpr int kCompositeBatch = 32;
 
-struct LevelSlots {           // per level, per lane
-  int reg, slot;
-  unsigned long long mask0, mask1;
-  bool has2;
-  float rg0, rg1;
-};
-
 template <int B>
 __global__ __launch_bounds__(64) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
@@ -56,6 +49,8 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
   __shared__ float E[B * kEStride];
+  __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
+  __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
   if (st->view_overflow) return;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -68,8 +63,9 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   const bool inside = px < W && py < H;
   // per level: the pixel's region (validated on every pixel, empty blocks
   // included) and the block's two record regions r0 = region of the first
-  // pixel with one, r1 = first other region
-  LevelSlots ls[kMaxLevels];
+  // pixel with one, r1 = first other region; pixels of further regions are
+  // flagged (has2) and handled after each batch
+  unsigned int has2 = 0u;                      // bit l: level l has pixels of a third region
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l) {
     if (l >= n_levels) break;
@@ -83,52 +79,49 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
     const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
     const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
-    ls[l].reg = reg;
-    ls[l].slot = reg < 0 ? 3 : reg == r0 ? 0 : reg == r1 ? 1 : 2;
-    ls[l].mask0 = __ballot(ls[l].slot == 0);
-    ls[l].mask1 = __ballot(ls[l].slot == 1);
-    ls[l].has2 = __ballot(ls[l].slot == 2) != 0ull;
-    ls[l].rg0 = __int_as_float(r0 >= 0 ? (int)(lv.region_base + r0) : -1);
-    ls[l].rg1 = __int_as_float(r1 >= 0 ? (int)(lv.region_base + r1) : -1);
+    const unsigned long long m0 = __ballot(reg >= 0 && reg == r0);
+    const unsigned long long m1 = __ballot(reg >= 0 && reg == r1);
+    if (__ballot(reg >= 0 && reg != r0 && reg != r1)) has2 |= 1u << l;
+    if (lane == 0) {
+      s_mask[l][0] = m0; s_mask[l][1] = m1;
+      s_rg[l][0] = __int_as_float(r0 >= 0 ? (int)(lv.region_base + r0) : -1);
+      s_rg[l][1] = __int_as_float(r1 >= 0 ? (int)(lv.region_base + r1) : -1);
+    }
   }
   if (L == 0) return;
+  __syncthreads();
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = 1.0f;
   bool done = !inside;
-  unsigned long long count = 0;
-  bool any_has2 = false;
-#pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l)
-    if (l < n_levels) any_has2 = any_has2 || ls[l].has2;
+  unsigned int count = 0u;                     // this pixel's contributions
   const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
   const int gq0 = lane - gk;                   // first pixel of the lane's group
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(!done) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
-    SplatLane mine;
+    BlockSplat mine;
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
     if (j < L) {                               // every lane group holds the batch's splats
       my_id = (unsigned int)keys[start + j];
       const GSplat gg = splats[my_id];
-      mine.load(gg);
+      mine.load(gg, tile_x0, tile_y0);
       own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
     }
     unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
     if (!all_done) {
       for (int k = 0; k < nb; ++k) {
-        const SplatLane g = mine.bcast(k);
-        const float hx = (float)(g.ix - tile_x0), hy = (float)(g.iy - tile_y0);
-        const float dx = (pcx - hx) - g.fx, dy = (pcy - hy) - g.fy;
+        const BlockSplat g = mine.bcast(k);
+        const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
         const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
         const float q = fmaf(u, u, v * v);
-        const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
-        const bool take = !done && alpha >= kAlphaMin;
+        const bool take = !done && q <= g.qmax;
         if (__ballot(take) == 0ull) continue;
         float e = 0.0f;
         if (take) {
+          const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
           const float testT = T * (1.0f - alpha);
           if (testT < kTMin) {
             done = true;
@@ -137,42 +130,10 @@ __global__ __launch_bounds__(64) void k_composite_blk(
             T = testT;
           }
         }
-        const unsigned long long cm = __ballot(e > 0.0f);
-        if (cm) {
+        count += e > 0.0f ? 1u : 0u;
+        if (__ballot(e > 0.0f)) {
           contributed |= 1ull << k;
-          count += (unsigned long long)__popcll(cm);
           E[k * kEStride + lane] = e;
-          if (any_has2) {   // third and further regions of a block: straight to the accumulator
-#pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-              if (l >= n_levels || !ls[l].has2) continue;
-              const LevelView& lv = args.lv[l];
-              const int reg = ls[l].reg;
-              unsigned long long rm = __ballot(e > 0.0f && ls[l].slot == 2);
-              const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
-              const unsigned long long row = (unsigned long long)idk * (unsigned long long)m_atoms;
-              while (rm) {
-                const int l0 = __ffsll((long long)rm) - 1;
-                const int rr = __builtin_amdgcn_readlane(reg, l0);
-                const unsigned long long same = __ballot(reg == rr) & rm;
-                const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
-                if (lv.dense_F) {      // dense feature uplift: w F_r and w
-                  const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
-                  const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
-                  for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
-                  if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
-                } else {
-                  const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
-                  for (int c = lane; c < lv.k_code; c += 64) {
-                    const int jj = lv.code_idx[gr + c];
-                    if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                    else if (jj >= 0) atomic_add_f32(&lv.acc[row + (unsigned long long)jj], sum * lv.code_val[gr + c]);
-                  }
-                }
-                rm &= ~same;
-              }
-            }
-          }
         }
         if (__ballot(!done) == 0ull) break;
       }
@@ -187,7 +148,7 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       if (l >= n_levels) break;
       float w0 = 0.0f, w1 = 0.0f;
       if (had) {
-        const unsigned long long m0 = ls[l].mask0 >> gq0, m1 = ls[l].mask1 >> gq0;
+        const unsigned long long m0 = s_mask[l][0] >> gq0, m1 = s_mask[l][1] >> gq0;
 #pragma unroll 8
         for (int q = 0; q < B; ++q) {
           const float x = row[q];
@@ -203,13 +164,55 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       if (lane < nb) {
         const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
         float2* rec = args.lv[l].records;
-        rec[2ull * p] = make_float2(ls[l].rg0, w0);
-        rec[2ull * p + 1] = make_float2(ls[l].rg1, w1);
+        rec[2ull * p] = make_float2(s_rg[l][0], w0);
+        rec[2ull * p + 1] = make_float2(s_rg[l][1], w1);
+      }
+    }
+    if (has2 && contributed) {   // third and further regions of the block: straight to the accumulator
+#pragma unroll
+      for (int l = 0; l < kMaxLevels; ++l) {
+        if (l >= n_levels || !((has2 >> l) & 1u)) continue;
+        const LevelView& lv = args.lv[l];
+        const int reg = inside ? lv.rmap[(long long)py * W + px] : -1;
+        const int r0 = __float_as_int(s_rg[l][0]), r1 = __float_as_int(s_rg[l][1]);
+        const int greg = reg >= 0 && reg < lv.n_regions ? (int)(lv.region_base + reg) : -1;
+        const bool third = greg >= 0 && greg != r0 && greg != r1;
+        unsigned long long km = contributed;
+        while (km) {
+          const int k = __ffsll((long long)km) - 1;
+          km &= km - 1;
+          const float e = E[k * kEStride + lane];
+          const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
+          unsigned long long rm = __ballot(third && e > 0.0f);
+          while (rm) {
+            const int l0 = __ffsll((long long)rm) - 1;
+            const int rr = __builtin_amdgcn_readlane(reg, l0);
+            const unsigned long long same = __ballot(reg == rr) & rm;
+            const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
+            if (lv.dense_F) {      // dense feature uplift: w F_r and w
+              const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
+              const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
+              for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
+              if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
+            } else {
+              const unsigned long long arow = (unsigned long long)idk * (unsigned long long)m_atoms;
+              const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
+              for (int c = lane; c < lv.k_code; c += 64) {
+                const int jj = lv.code_idx[gr + c];
+                if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+                else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+              }
+            }
+            rm &= ~same;
+          }
+        }
       }
     }
     __syncthreads();
   }
-  if (lane == 0 && count) atomicAdd(&st->contrib, count);   // count is wave-uniform
+  unsigned long long total = count;
+  for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
+  if (lane == 0 && total) atomicAdd(&st->contrib, total);
 }
 
 // Eq. 6 on one row held by a wave (values in LDS or global memory).
