@@ -39,8 +39,8 @@ int tiles_of(int w, int h, int shift = 4) {
 
 // Workspace layout of one binning pass (+ the uplift's per-view offsets and records).
 struct BinLayout {
-  size_t status, splats, offsets, scan_part, tile_start, big_tiles, bin_hist, radix_hist, tile_ids[2], keys[2],
-      records, total;
+  size_t status, splats, offsets, scan_part, tile_start, big_tiles, tile_order, bin_hist, radix_hist, tile_ids[2],
+      keys[2], records, total;
   bool counting;
 };
 
@@ -56,6 +56,7 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
   L.scan_part = off; off = align256(off + 8 * (size_t)std::max<long long>(1, sparts));
   L.tile_start = off; off = align256(off + 4 * (size_t)(max_tiles + 1));
   L.big_tiles = off; off = align256(off + 4 * (size_t)max_tiles);
+  L.tile_order = off; off = align256(off + 4 * (size_t)max_tiles);
   L.counting = count_binning_ok(n, max_tiles);
   L.bin_hist = off;
   if (L.counting) off = align256(off + 4 * (size_t)count_groups(n) * (size_t)max_tiles);
@@ -95,6 +96,7 @@ void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const BinLayout&
   b.scan_part = reinterpret_cast<unsigned long long*>(base + L.scan_part);
   b.tile_start = reinterpret_cast<unsigned int*>(base + L.tile_start);
   b.big_tiles = reinterpret_cast<unsigned int*>(base + L.big_tiles);
+  b.tile_order = reinterpret_cast<unsigned int*>(base + L.tile_order);
   b.bin_hist = L.counting ? reinterpret_cast<unsigned int*>(base + L.bin_hist) : nullptr;
   b.radix_hist = reinterpret_cast<unsigned int*>(base + L.radix_hist);
   for (int k = 0; k < 2; ++k) {

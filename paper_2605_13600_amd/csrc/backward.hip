@@ -20,6 +20,7 @@ constexpr int kBwdKMax = 16;
 // LDS, reduce over the block's pixels and add to grad_val.
 __global__ __launch_bounds__(64) void k_render_bwd(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
+    const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
     const int* __restrict__ topk_idx, int K, int M, const float* __restrict__ dW,
     float* __restrict__ grad_val, Status* st) {
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   __shared__ unsigned int s_id[64];
   __shared__ int s_ti[64 * kBwdKMax];
   if (st->view_overflow) return;
-  const int tile = blockIdx.x;
+  const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
@@ -154,7 +155,7 @@ hipError_t launch_render_bwd_view(RenderBwdArgs& a, hipStream_t s) {
   const BinArgs& b = a.bin;
   const size_t lds = sizeof(float) * 64 * (size_t)(a.m_atoms + 1);
   StageTimer::begin(kStRenderBwd, s);
-  hipLaunchKernelGGL(k_render_bwd, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start, b.keys[b.sorted],
+  hipLaunchKernelGGL(k_render_bwd, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start, b.tile_order, b.keys[b.sorted],
                      b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.k, a.m_atoms, a.dW,
                      a.grad_val, b.status);
   StageTimer::end(kStRenderBwd, s);

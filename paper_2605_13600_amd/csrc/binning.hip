@@ -545,8 +545,52 @@ int radix_passes(int n_tiles) {
 long long radix_blocks(long long capacity) { return (capacity + kRadixBlock - 1) / kRadixBlock; }
 long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
 
+// Processing order of the tiles for the compositing kernels: longest list
+// first (lists of 2047 or more pairs share the first bucket), so that the
+// blocks with the longest sequential loops start at the beginning of the
+// launch instead of setting its tail.  One workgroup; a counting sort on the
+// clamped length.
+constexpr int kOrderBuckets = 2048;
+
+__global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restrict__ tile_start, int n_tiles,
+                                                     unsigned int* __restrict__ order, const Status* st) {
+  __shared__ unsigned int h[kOrderBuckets];
+  __shared__ unsigned int part[1024];
+  const int tid = threadIdx.x;
+  if (st->view_overflow) {
+    for (int t = tid; t < n_tiles; t += 1024) order[t] = (unsigned int)t;
+    return;
+  }
+  for (int b = tid; b < kOrderBuckets; b += 1024) h[b] = 0u;
+  __syncthreads();
+  auto bucket = [&](int t) {
+    const unsigned int L = tile_start[t + 1] - tile_start[t];
+    return kOrderBuckets - 1 - (int)min(L, (unsigned int)(kOrderBuckets - 1));
+  };
+  for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&h[bucket(t)], 1u);
+  __syncthreads();
+  // exclusive scan of the buckets: two per thread, then across threads
+  const unsigned int c0 = h[2 * tid], c1 = h[2 * tid + 1];
+  part[tid] = c0 + c1;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned int v = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  const unsigned int before = part[tid] - (c0 + c1);
+  __syncthreads();
+  h[2 * tid] = before;
+  h[2 * tid + 1] = before + c0;
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[bucket(t)], 1u)] = (unsigned int)t;
+}
+
 // depth order inside every tile list of the sorted buffer
 static void sort_lists(const BinArgs& a, hipStream_t s) {
+  if (a.tile_order && a.n_tiles > 0)
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.tile_order, a.status);
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
                      a.status);
   if (a.n_tiles > 0) {            // lists of 2..512 and 513..kSortCap pairs

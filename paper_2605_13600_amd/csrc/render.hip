@@ -20,6 +20,7 @@ __device__ __forceinline__ void store_out(uint8_t* p, float v) { *p = f32_to_e4m
 template <typename OutT>
 __global__ __launch_bounds__(64) void k_render_coeff(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
+    const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
     const int* __restrict__ topk_idx, const float* __restrict__ topk_val, int K, int M,
     OutT* __restrict__ out, float out_scale, float* __restrict__ t_final, Status* st) {
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(64) void k_render_coeff(
   __shared__ int s_ti[64 * kRenderKMax];
   __shared__ float s_tv[64 * kRenderKMax];
   if (st->view_overflow) return;
-  const int tile = blockIdx.x;
+  const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
@@ -113,18 +114,18 @@ hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
   switch (a.out_dtype) {
     case SCOUP_F32:
       hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start,
-                         b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
+                         b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
                          a.m_atoms, (float*)a.out, a.out_scale, a.t_final, b.status);
       break;
     case SCOUP_BF16:
       hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
-                         b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, (uint16_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;
     default:
       hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
-                         b.tile_start, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
+                         b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, (uint8_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;

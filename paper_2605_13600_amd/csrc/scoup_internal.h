@@ -37,6 +37,7 @@ struct BinArgs {
   unsigned int* radix_hist;        // [128 * radix blocks]
   unsigned int* tile_start;        // [n_tiles + 1]
   unsigned int* big_tiles;         // [n_tiles] tiles longer than sort_cap
+  unsigned int* tile_order;        // [n_tiles] tiles by descending list length (compositing order)
   unsigned int* bin_hist;          // [count_groups(n) x n_tiles] counting-pass bases, or NULL (radix path)
   long long capacity;
   Status* status;

@@ -45,6 +45,7 @@ constexpr int kCompositeBatch = 32;
 template <int B>
 __global__ __launch_bounds__(64) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
+    const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
   __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
   if (st->view_overflow) return;
-  const int tile = blockIdx.x;
+  const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
@@ -454,7 +455,7 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
   hipLaunchKernelGGL(k_composite_blk<kCompositeBatch>, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
-                     b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
+                     b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
   StageTimer::end(kStComposite, s);
   return hipGetLastError();
