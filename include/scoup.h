@@ -199,7 +199,7 @@ size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam
  *   coeff_map  device [H*W*m_atoms] of coeff_dtype, pixel-major (y*W + x)
  *   t_final    device float32 [H*W] transmittance left at each pixel, or NULL
  *   n_contrib  device uint64 [1] (+=) contributions composited, or NULL
- * Requires 1 <= m_atoms <= 1024.                                             */
+ * Requires 1 <= m_atoms <= 512 (64 pixel rows of m_atoms floats in LDS).    */
 scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx,
                                 const float* topk_val, int32_t k, int32_t m_atoms,
                                 const scoup_camera* cam, void* coeff_map, scoup_dtype coeff_dtype,

@@ -539,7 +539,7 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
   if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
   if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
-  if (m_atoms < 1 || m_atoms > 1024) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 1024]");
+  if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
   if (coeff_dtype != SCOUP_F32 && coeff_dtype != SCOUP_BF16 && coeff_dtype != SCOUP_FP8_E4M3)
     return fail(SCOUP_E_ARG, "unknown coefficient dtype");
   if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
@@ -674,7 +674,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
   if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
   if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
-  if (m_atoms < 1 || m_atoms > 1024) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 1024]");
+  if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
   if (dim < 1 || dim > 4096) return fail(SCOUP_E_ARG, "dim must be in [1, 4096]");
   if (!coeff_map || !codebook || !grad_features || !grad_codebook)
     return fail(SCOUP_E_ARG, "a backward array is NULL");

@@ -17,50 +17,63 @@ __device__ __forceinline__ void store_out(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_out(uint16_t* p, float v) { *p = f32_to_bf16_rne(v); }
 __device__ __forceinline__ void store_out(uint8_t* p, float v) { *p = f32_to_e4m3(v); }
 
+// Four waves per 8x8 block share its LDS rows: wave w composites pixel rows
+// 2w and 2w+1 (16 pixels, lane & 15), and the four lane groups of 16 (lane >> 4)
+// each add every fourth code slot of a contributing Gaussian.  The front-to-
+// back recurrence is evaluated by all four lane groups of a pixel (no cross-lane
+// traffic); what the split buys is four waves in flight per block instead of one,
+// since the block's 64 KB of rows allow only two blocks per CU.
+constexpr int kRenderWaves = 4;
+constexpr int kRenderBatch = 16;          // Gaussians staged per wave and batch
+
+// order of one wave's own LDS writes before its reads (and reads before rewrites)
+__device__ __forceinline__ void render_wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 template <typename OutT>
-__global__ __launch_bounds__(64) void k_render_coeff(
+__global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, int tiles_x, int W, int H,
     const int* __restrict__ topk_idx, const float* __restrict__ topk_val, int K, int M,
     OutT* __restrict__ out, float out_scale, float* __restrict__ t_final, Status* st) {
   extern __shared__ float rows[];          // 64 * (M+1) floats
-  __shared__ int s_ti[64 * kRenderKMax];
-  __shared__ float s_tv[64 * kRenderKMax];
+  __shared__ int s_ti[kRenderWaves][kRenderBatch * kRenderKMax];
+  __shared__ float s_tv[kRenderWaves][kRenderBatch * kRenderKMax];
   if (st->view_overflow) return;
   const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
-  const int lane = threadIdx.x;
-  const int lx = lane & 7, ly = lane >> 3;
-  const int px = tx * 8 + lx, py = ty * 8 + ly;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int pix = wave * 16 + (lane & 15), sub = lane >> 4;
+  const int lx = pix & 7, ly = pix >> 3;
+  const int tile_x0 = tx * 8, tile_y0 = ty * 8;
+  const int px = tile_x0 + lx, py = tile_y0 + ly;
   const bool inside = px < W && py < H;
   const int stride = M + 1;
 
-  for (int j = lane; j < 64 * stride; j += 64) rows[j] = 0.0f;
+  for (int j = tid; j < 64 * stride; j += 64 * kRenderWaves) rows[j] = 0.0f;
   __syncthreads();
 
-  float* myrow = rows + lane * stride;
+  float* myrow = rows + pix * stride;
+  int* ti = s_ti[wave];
+  float* tv = s_tv[wave];
   float T = 1.0f;
   bool done = !inside;
-  unsigned long long count = 0;
+  unsigned int count = 0u;
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
-  const int tile_x0 = tx * 8, tile_y0 = ty * 8;
-  for (int b0 = 0; b0 < L; b0 += 64) {
+  for (int b0 = 0; b0 < L; b0 += kRenderBatch) {
     if (__ballot(!done) == 0ull) break;
-    const int j = b0 + lane;
+    const int nb = min(kRenderBatch, L - b0);
     BlockSplat mine;
-    if (j < L) {
-      const unsigned int id = (unsigned int)keys[start + j];
-      mine.load(splats[id], tile_x0, tile_y0);
-      for (int k = 0; k < K; ++k) {
-        s_ti[lane * K + k] = topk_idx[(long long)id * K + k];
-        s_tv[lane * K + k] = topk_val[(long long)id * K + k];
-      }
+    if (lane < nb) mine.load(splats[(unsigned int)keys[start + b0 + lane]], tile_x0, tile_y0);
+    for (int t = lane; t < nb * K; t += 64) {
+      const int k = t / K, j = t - k * K;
+      const long long id = (long long)(unsigned int)keys[start + b0 + k];
+      ti[t] = topk_idx[id * K + j];
+      tv[t] = topk_val[id * K + j];
     }
-    __syncthreads();
-    const int nb = min(64, L - b0);
+    render_wave_lds_sync();
     for (int k = 0; k < nb; ++k) {
       const BlockSplat g = mine.bcast(k);
       const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
@@ -80,23 +93,25 @@ __global__ __launch_bounds__(64) void k_render_coeff(
         }
       }
       if (e > 0.0f) {
-        ++count;
-        for (int kk = 0; kk < K; ++kk) {   // fire-and-forget LDS adds: no read-modify-write chain
-          const int jj = s_ti[k * K + kk];
-          if (jj >= 0 && jj < M) atomicAdd(&myrow[jj], e * s_tv[k * K + kk]);
+        count += sub == 0 ? 1u : 0u;
+        for (int kk = sub; kk < K; kk += 4) {   // fire-and-forget LDS adds: no read-modify-write chain
+          const int jj = ti[k * K + kk];
+          if (jj >= 0 && jj < M) atomicAdd(&myrow[jj], e * tv[k * K + kk]);
           else if (jj >= M) atomicOr(&st->data_error, 4u);
         }
       }
       if (__ballot(!done) == 0ull) break;
     }
-    __syncthreads();
+    render_wave_lds_sync();
   }
-  if (inside && t_final) t_final[(long long)py * W + px] = T;
-  // contributions: one atomic per wave
-  for (int o = 32; o >= 1; o >>= 1) count += __shfl_xor(count, o, 64);
-  if (lane == 0 && count) atomicAdd(&st->contrib, count);
-  // write the 8x8 block's rows, atoms fastest (coalesced per pixel row)
-  for (int p = 0; p < 64; ++p) {
+  if (inside && sub == 0 && t_final) t_final[(long long)py * W + px] = T;
+  unsigned long long total = count;
+  for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
+  if (lane == 0 && total) atomicAdd(&st->contrib, total);
+  // this wave's 16 pixel rows are complete (its own LDS adds are ordered before
+  // these reads); write them, atoms fastest (coalesced per pixel row)
+  render_wave_lds_sync();
+  for (int p = wave * 16; p < wave * 16 + 16; ++p) {
     const int ox = tile_x0 + (p & 7), oy = tile_y0 + (p >> 3);
     if (ox >= W || oy >= H) continue;
     OutT* dst = out + ((long long)oy * W + ox) * M;
@@ -113,18 +128,18 @@ hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
   StageTimer::begin(kStRender, s);
   switch (a.out_dtype) {
     case SCOUP_F32:
-      hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64), lds, s, b.splats, b.tile_start,
+      hipLaunchKernelGGL(k_render_coeff<float>, dim3(b.n_tiles), dim3(64 * kRenderWaves), lds, s, b.splats, b.tile_start,
                          b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx, a.topk_val, a.k,
                          a.m_atoms, (float*)a.out, a.out_scale, a.t_final, b.status);
       break;
     case SCOUP_BF16:
-      hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
+      hipLaunchKernelGGL(k_render_coeff<uint16_t>, dim3(b.n_tiles), dim3(64 * kRenderWaves), lds, s, b.splats,
                          b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, (uint16_t*)a.out, a.out_scale,
                          a.t_final, b.status);
       break;
     default:
-      hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64), lds, s, b.splats,
+      hipLaunchKernelGGL(k_render_coeff<uint8_t>, dim3(b.n_tiles), dim3(64 * kRenderWaves), lds, s, b.splats,
                          b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.topk_idx,
                          a.topk_val, a.k, a.m_atoms, (uint8_t*)a.out, a.out_scale,
                          a.t_final, b.status);
@@ -135,7 +150,7 @@ hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s) {
 }
 
 hipError_t render_set_lds_limits() {
-  const int bytes = 160 * 1024 - (int)(8 * 64 * kRenderKMax) - 1024;
+  const int bytes = 160 * 1024 - (int)(8 * kRenderWaves * kRenderBatch * kRenderKMax) - 1024;
   hipError_t e = hipFuncSetAttribute((const void*)k_render_coeff<float>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
