@@ -256,6 +256,46 @@ def bench_levels_and_dense(sc, P, sg, torch, np, dense_views=20):
     return out
 
 
+def bench_backward(lib, P, sg, torch, np, n_views=8):
+    """Backward of render + decode (float32) on the backward workload: 200,000
+    Gaussians, Top-8 over M=256, codebook 256x512, 8 orbit views of 512x384;
+    a seeded N(0,1) feature gradient stands in for dL/dF.  HIP-event time of
+    the render-backward kernel and of the two GEMMs (dW = G C^T, dC = W^T G)."""
+    n, m, d, k = 200_000, 256, 512, 8
+    g = sg.make_gaussians(1003, n, (5.0, 5.0, 2.0), -4.5, 0.5, False, "beta")
+    cams = sg.orbit_cameras(1004, n_views, 12.0, 0.0, 4.0, 0.0, 0.0, 512, 384, 60.0, jitter=False)
+    ti, tv = sg.random_topk(1005, n, m, k)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    dC = torch.from_numpy(sg.random_codebook(1006, m, d)).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(1007)
+    G = torch.randn((384 * 512, d), device="cuda", generator=gen)
+    maps = [P.render_coeff(dg, dti, dtv, cam, m, dtype="f32", want_t_final=False)[0] for cam in cams]
+    gw, gc = torch.zeros_like(dtv), torch.zeros_like(dC)
+    P.render_backward(dg, dti, dtv, cams[0], maps[0], dC, G, gw, gc)      # warm-up
+    torch.cuda.synchronize()
+    lib.scoup_stage_timing(1)
+    t0 = time.perf_counter()
+    for cam, W in zip(cams, maps):
+        P.render_backward(dg, dti, dtv, cam, W, dC, G, gw, gc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot, cnt = C_double(), C_int64()
+    lib.scoup_stage_stats(8, C_byref(tot), C_byref(cnt))
+    bwd_us = tot.value * 1e3 / max(1, cnt.value)
+    lib.scoup_stage_stats(9, C_byref(tot), C_byref(cnt))
+    gemm_ms = tot.value / max(1, n_views)
+    lib.scoup_stage_timing(0)
+    px = 384 * 512
+    gemm_tf = 2 * 2.0 * px * m * d / (gemm_ms * 1e-3) / 1e12
+    out = {"workload": f"backward: {n} Gaussians, Top-{k} over M={m}, codebook {m}x{d}, {n_views} views 512x384",
+           "ms_per_view": round(wall * 1e3 / n_views, 3), "mpix_s": round(px * n_views / wall / 1e6, 2),
+           "render_backward_avg_us": round(bwd_us, 2), "gemms_ms_per_view": round(gemm_ms, 3),
+           "gemm_tflops_f32": round(gemm_tf, 2), "gemm_mfma_frac": round(gemm_tf / 157.3, 4)}
+    log(f"backward: {out}")
+    return out
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling rocprof's FETCH_SIZE /
     WRITE_SIZE counters (the dispatch appears in the same profile)."""
@@ -279,6 +319,7 @@ def main():
     ap.add_argument("--decode-sweep", type=int, default=1, help="time decode for M in 64..512 (0 = skip)")
     ap.add_argument("--extras", type=int, default=1,
                     help="three-level pass and dense-vs-sparse uplift sections (0 = skip)")
+    ap.add_argument("--backward", type=int, default=1, help="time the render + decode backward (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling HBM counters in a profile)")
     args = ap.parse_args()
@@ -355,6 +396,7 @@ def main():
         copy_calibration(torch)
     sweep = bench_decode_sweep(lib, P, sg, torch, np) if args.decode_sweep else None
     extras = bench_levels_and_dense(sc, P, sg, torch, np) if args.extras else None
+    backward = bench_backward(lib, P, sg, torch, np) if args.backward else None
 
     render = None
     if args.render_views > 0:
@@ -392,6 +434,7 @@ def main():
         "render_decode": render,
         "decode_sweep": sweep,
         "extras": extras,
+        "backward": backward,
     }
     print(json.dumps(out), flush=True)
 

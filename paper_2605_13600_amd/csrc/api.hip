@@ -328,8 +328,10 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         b.tiles_x = (c.width + 7) / 8;
         b.n_tiles = tiles_of(c.width, c.height, 3);
         b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
+        b.n_cull_records = n_levels;
         for (int l = 0; l < n_levels; ++l) {
           a.lv[l].records = rec_all + ((size_t)l * vb + j) * rec_view;
+          b.cull_records[l] = a.lv[l].records;
           a.lv[l].rmap = lvs[l].region_maps + lvs[l].map_offsets[i];
           a.lv[l].n_regions = (int)(lvs[l].region_base[i + 1] - lvs[l].region_base[i]);
           a.lv[l].region_base = lvs[l].region_base[i];
@@ -470,6 +472,8 @@ scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, 
         b.n_tiles = tiles_of(c.width, c.height, 3);
         b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
         lv.records = rec_all + (size_t)j * 2 * (size_t)pair_capacity;
+        b.n_cull_records = 1;
+        b.cull_records[0] = lv.records;
         lv.rmap = v->region_maps + v->map_offsets[i];
         lv.n_regions = (int)(v->region_base[i + 1] - v->region_base[i]);
         lv.region_base = v->region_base[i];

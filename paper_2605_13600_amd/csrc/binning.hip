@@ -28,6 +28,14 @@ constexpr int kCountThreads = 512;
 constexpr int kCountGroups = 256;          // workgroups of the counting pass (at least)
 constexpr int kCountMaxTiles = 49152;      // 16-bit LDS counters: 96 KB
 
+// the uplift's record arrays of the current view, per level (pairs whose
+// block the Gaussian cannot reach are never composited: zero records)
+struct CullRecords {
+  float2* rec[4];
+  int n;
+};
+
+
 // ---------------------------------------------------------------------------
 // projection (one thread per Gaussian), FP64 arithmetic, FP32 storage
 // ---------------------------------------------------------------------------
@@ -238,8 +246,11 @@ __global__ __launch_bounds__(256) void k_scan_down(unsigned int* __restrict__ da
 // ---------------------------------------------------------------------------
 // Gaussian-major pair emission
 // ---------------------------------------------------------------------------
+// Blocks the Gaussian cannot reach get the tile id n_tiles, which sorts after
+// every list and belongs to none, and zero uplift records.
 __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n, int tiles_x,
-                                              int tile_shift, const unsigned int* __restrict__ off,
+                                              int n_tiles, int tile_shift, int W, int H,
+                                              const unsigned int* __restrict__ off, CullRecords cull,
                                               unsigned int* __restrict__ tile_ids,
                                               unsigned long long* __restrict__ keys, const Status* st) {
   if (st->view_overflow) return;
@@ -253,8 +264,14 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
   unsigned int p = off[i];
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx, ++p) {
-      tile_ids[p] = (unsigned int)(ty * tiles_x + tx);
+      const bool live = block_live(s, tx, ty, tile_shift, W, H);
+      tile_ids[p] = live ? (unsigned int)(ty * tiles_x + tx) : (unsigned int)n_tiles;
       keys[p] = key;
+      if (!live)
+        for (int l = 0; l < cull.n; ++l) {
+          cull.rec[l][2ull * p] = make_float2(__int_as_float(-1), 0.0f);
+          cull.rec[l][2ull * p + 1] = make_float2(__int_as_float(-1), 0.0f);
+        }
     }
 }
 
@@ -269,7 +286,7 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
 // independent of it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __restrict__ splats, long long n,
-                                                             int tiles_x, int n_tiles, int tile_shift,
+                                                             int tiles_x, int n_tiles, int tile_shift, int W, int H,
                                                              long long per_wg, unsigned int* __restrict__ hist,
                                                              const Status* st) {
   extern __shared__ unsigned int h[];                // ceil(n_tiles / 2) words
@@ -286,6 +303,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
     for (int ty = ty0; ty <= ty1; ++ty)
       for (int tx = tx0; tx <= tx1; ++tx) {
+        if (!block_live(g, tx, ty, tile_shift, W, H)) continue;
         const int t = ty * tiles_x + tx;
         atomicAdd(&h[t >> 1], 1u << (16 * (t & 1)));
       }
@@ -322,7 +340,8 @@ __global__ __launch_bounds__(256) void k_bin_colscan(unsigned int* __restrict__ 
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __restrict__ splats, long long n,
-                                                             int tiles_x, int n_tiles, int tile_shift,
+                                                             int tiles_x, int n_tiles, int tile_shift, int W, int H,
+                                                             const unsigned int* __restrict__ off, CullRecords cull,
                                                              long long per_wg, const unsigned int* __restrict__ hist,
                                                              const unsigned int* __restrict__ tile_start,
                                                              unsigned long long* __restrict__ keys,
@@ -341,8 +360,16 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
     const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
+    unsigned int p = off[i];                   // Gaussian-major pair index (uplift records)
     for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
+      for (int tx = tx0; tx <= tx1; ++tx, ++p) {
+        if (!block_live(g, tx, ty, tile_shift, W, H)) {
+          for (int l = 0; l < cull.n; ++l) {
+            cull.rec[l][2ull * p] = make_float2(__int_as_float(-1), 0.0f);
+            cull.rec[l][2ull * p + 1] = make_float2(__int_as_float(-1), 0.0f);
+          }
+          continue;
+        }
         const int t = ty * tiles_x + tx;
         const unsigned int sh = 16 * (t & 1);
         const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
@@ -515,25 +542,63 @@ __global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restric
   }
 }
 
-// Depth order inside every block list of lo < L <= hi pairs: one workgroup of
-// NT threads per block, bitonic network over the list in LDS (ascending
-// (depth, id)).  Short lists (the common case) run in one-wave workgroups
-// with a small static LDS buffer, so many blocks sort concurrently per CU.
-template <int NT, int CAP>
+// Depth order inside every block list: one workgroup of NT threads per block
+// whose list has hi/2 < L <= hi = NT x PER pairs (one launch per size class),
+// a bitonic network over hi keys (the list padded with ~0).  Thread t keeps
+// elements t PER .. t PER + PER - 1 in registers: compare-exchange distances
+// below PER stay in registers; longer ones go through LDS, stored element-
+// slot-major (slot r of thread t at r NT + t) so that a wave's accesses are
+// consecutive.
+template <int PER, int J>
+__device__ __forceinline__ void bitonic_regs(unsigned long long (&v)[PER], int base, int k) {
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if ((r & J) == 0) {
+      const unsigned long long a = v[r], b = v[r ^ J];
+      const bool asc = ((base + r) & k) == 0;
+      const bool sw = asc ? (a > b) : (a < b);
+      v[r] = sw ? b : a;
+      v[r ^ J] = sw ? a : b;
+    }
+  }
+}
+
+template <int NT, int PER>
 __global__ __launch_bounds__(NT) void k_sort_blocks(unsigned long long* __restrict__ keys,
                                                     const unsigned int* __restrict__ tile_start, int lo,
                                                     const Status* st) {
-  __shared__ unsigned long long sk[CAP];
+  constexpr int HI = NT * PER;
+  __shared__ unsigned long long sk[HI];
   if (st->view_overflow) return;
   const unsigned int start = tile_start[blockIdx.x];
   const int L = (int)(tile_start[blockIdx.x + 1] - start);
-  if (L <= lo || L > CAP) return;
-  int n2 = 1;
-  while (n2 < L) n2 <<= 1;
-  for (int j = threadIdx.x; j < n2; j += NT) sk[j] = j < L ? keys[start + j] : ~0ull;
-  __syncthreads();
-  bitonic_lds(sk, n2, threadIdx.x, NT);
-  for (int j = threadIdx.x; j < L; j += NT) keys[start + j] = sk[j];
+  if (L <= lo || L > HI) return;
+  const int t = threadIdx.x, base = t * PER;
+  unsigned long long v[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) v[r] = base + r < L ? keys[start + base + r] : ~0ull;
+  for (int k = 2; k <= HI; k <<= 1) {
+    for (int j = k >> 1; j >= PER; j >>= 1) {      // partner in thread t ^ (j / PER), same slot
+#pragma unroll
+      for (int r = 0; r < PER; ++r) sk[r * NT + t] = v[r];
+      __syncthreads();
+      const int pt = t ^ (j / PER);
+      const bool lower = (base & j) == 0;
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const unsigned long long w = sk[r * NT + pt];
+        const bool asc = ((base + r) & k) == 0;
+        v[r] = (asc == lower) ? (v[r] < w ? v[r] : w) : (v[r] > w ? v[r] : w);
+      }
+      __syncthreads();
+    }
+    if (PER >= 8 && k >= 8) bitonic_regs<PER, (PER >= 8 ? 4 : 1)>(v, base, k);
+    if (PER >= 4 && k >= 4) bitonic_regs<PER, (PER >= 4 ? 2 : 1)>(v, base, k);
+    if (PER >= 2) bitonic_regs<PER, 1>(v, base, k);
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r)
+    if (base + r < L) keys[start + base + r] = v[r];
 }
 
 int radix_passes(int n_tiles) {
@@ -587,17 +652,28 @@ __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restr
   for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[bucket(t)], 1u)] = (unsigned int)t;
 }
 
+static CullRecords cull_of(const BinArgs& a) {
+  CullRecords c{};
+  c.n = std::min(a.n_cull_records, 4);
+  for (int l = 0; l < c.n; ++l) c.rec[l] = a.cull_records[l];
+  return c;
+}
+
 // depth order inside every tile list of the sorted buffer
 static void sort_lists(const BinArgs& a, hipStream_t s) {
   if (a.tile_order && a.n_tiles > 0)
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.tile_order, a.status);
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
                      a.status);
-  if (a.n_tiles > 0) {            // lists of 2..512 and 513..kSortCap pairs
-    hipLaunchKernelGGL((k_sort_blocks<64, 512>), dim3(a.n_tiles), dim3(64), 0, s, a.keys[a.sorted], a.tile_start,
-                       1, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<256, kSortCap>), dim3(a.n_tiles), dim3(256), 0, s, a.keys[a.sorted],
-                       a.tile_start, 512, a.status);
+  if (a.n_tiles > 0) {            // size classes 2..128, 129..256, ..., 2049..4096 (= kSortCap)
+    unsigned long long* k = a.keys[a.sorted];
+    const dim3 g(a.n_tiles);
+    hipLaunchKernelGGL((k_sort_blocks<64, 2>), g, dim3(64), 0, s, k, a.tile_start, 1, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<64, 4>), g, dim3(64), 0, s, k, a.tile_start, 128, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<64, 8>), g, dim3(64), 0, s, k, a.tile_start, 256, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<128, 8>), g, dim3(128), 0, s, k, a.tile_start, 512, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<256, 8>), g, dim3(256), 0, s, k, a.tile_start, 1024, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<512, 8>), g, dim3(512), 0, s, k, a.tile_start, 2048, a.status);
   }
 }
 
@@ -621,7 +697,8 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   const bool counting = a.bin_hist && count_binning_ok(a.n, a.n_tiles);
   if (a.n > 0 && !counting) {
     StageTimer::begin(kStEmit, s);
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.tile_shift, a.offsets,
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.n_tiles, a.tile_shift,
+                       a.cam.width, a.cam.height, (const unsigned int*)a.offsets, cull_of(a),
                        a.tile_ids[0], a.keys[0], a.status);
     StageTimer::end(kStEmit, s);
   }
@@ -631,7 +708,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     const long long per_wg = std::max<long long>(1, (a.n + nwg - 1) / nwg);
     const size_t lds = sizeof(unsigned int) * (size_t)((a.n_tiles + 1) / 2);
     hipLaunchKernelGGL(k_bin_count, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
-                       a.tile_shift, per_wg, a.bin_hist, a.status);
+                       a.tile_shift, a.cam.width, a.cam.height, per_wg, a.bin_hist, a.status);
     hipLaunchKernelGGL(k_bin_colscan, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.bin_hist, nwg, a.n_tiles,
                        a.tile_start, a.status);
     const int tsb = (int)scan_blocks(a.n_tiles);
@@ -640,8 +717,8 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_down, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part,
                        a.tile_start + a.n_tiles);
     hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
-                       a.tile_shift, per_wg, (const unsigned int*)a.bin_hist, (const unsigned int*)a.tile_start,
-                       a.keys[0], a.status);
+                       a.tile_shift, a.cam.width, a.cam.height, (const unsigned int*)a.offsets, cull_of(a), per_wg,
+                       (const unsigned int*)a.bin_hist, (const unsigned int*)a.tile_start, a.keys[0], a.status);
     hipLaunchKernelGGL(k_bin_big, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.tile_start, a.n_tiles,
                        a.sort_cap, a.big_tiles, a.status);
     a.sorted = 0;
@@ -650,7 +727,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   // radix sort by tile id: passes alternate between the two buffers
-  const int passes = radix_passes(a.n_tiles);
+  const int passes = radix_passes(a.n_tiles + 1);   // tile ids 0..n_tiles (n_tiles: unreachable block)
   const int rb = (int)radix_blocks(a.capacity);
   const long long hlen = (long long)rb * kRadixBins;
   const int hsb = (int)scan_blocks(hlen);

@@ -33,6 +33,35 @@ struct __align__(16) GSplat {
 };
 static_assert(sizeof(GSplat) == 48, "GSplat layout");
 
+// Whether Gaussian g can reach alpha >= 1/255 at any pixel centre of block
+// (bx, by) (edge 1 << shift pixels, clipped to the W x H image): the minimum
+// of q over the rectangle of pixel centres is zero if the centre lies inside,
+// else the smallest of the four edge minima (each a clamped 1D quadratic).
+// Conservative: a block is dropped only if that minimum exceeds log2(255 o)
+// by a relative 1e-4 (plus 1e-4), far beyond float32 rounding of either side.
+__device__ __forceinline__ bool block_live(const GSplat& g, int bx, int by, int shift, int W, int H) {
+  const int x_lo = bx << shift, y_lo = by << shift;
+  const int x_hi = min(x_lo + (1 << shift), W) - 1, y_hi = min(y_lo + (1 << shift), H) - 1;
+  const float xa = ((float)(x_lo - g.ix) + 0.5f) - g.fx, xb = ((float)(x_hi - g.ix) + 0.5f) - g.fx;
+  const float ya = ((float)(y_lo - g.iy) + 0.5f) - g.fy, yb = ((float)(y_hi - g.iy) + 0.5f) - g.fy;
+  if (xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f) return true;
+  const float a = g.l00, b = g.l10, c = g.l11;
+  auto q = [&](float dx, float dy) {
+    const float u = fmaf(a, dx, b * dy), v = c * dy;
+    return fmaf(u, u, v * v);
+  };
+  // horizontal edges dy = ya, yb: minimum at dx = -b dy / a
+  const float h0 = q(fminf(fmaxf(-b * ya / a, xa), xb), ya);
+  const float h1 = q(fminf(fmaxf(-b * yb / a, xa), xb), yb);
+  // vertical edges dx = xa, xb: minimum at dy = -a b dx / (b^2 + c^2)
+  const float den = fmaf(b, b, c * c);
+  const float v0 = q(xa, fminf(fmaxf(-a * b * xa / den, ya), yb));
+  const float v1 = q(xb, fminf(fmaxf(-a * b * xb / den, ya), yb));
+  const float qmin = fminf(fminf(h0, h1), fminf(v0, v1));
+  const float qmax = log2f(255.0f * g.opacity);
+  return qmin <= fmaf(qmax, 1.0001f, 1e-4f);
+}
+
 // The fields of a GSplat that compositing needs, held by the lane that loaded
 // it; bcast(k) reads lane k's copy into every lane via SGPRs (v_readlane), so
 // the sequential per-Gaussian loop does not wait on LDS.

@@ -38,6 +38,8 @@ struct BinArgs {
   unsigned int* tile_start;        // [n_tiles + 1]
   unsigned int* big_tiles;         // [n_tiles] tiles longer than sort_cap
   unsigned int* tile_order;        // [n_tiles] tiles by descending list length (compositing order)
+  float2* cull_records[4];         // uplift: per level, the view's records; pairs whose block the
+  int n_cull_records;              // Gaussian cannot reach get zero records here (0 levels: none)
   unsigned int* bin_hist;          // [count_groups(n) x n_tiles] counting-pass bases, or NULL (radix path)
   long long capacity;
   Status* status;
