@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_project(
   s.ix = 0; s.iy = 0; s.fx = 0.f; s.fy = 0.f;
   s.l00 = 0.f; s.l10 = 0.f; s.l11 = 0.f; s.opacity = 0.f;
   s.bx0 = 1; s.bx1 = 0; s.by0 = 1; s.by1 = 0;   // empty box = invisible
-  s.depth_bits = 0u; s.pad = 0u;
+  s.depth_bits = 0u; s.live = 0u;
   unsigned int nt = 0;
 
   const double mx = means[3 * i + 0], my = means[3 * i + 1], mz = means[3 * i + 2];
@@ -134,9 +134,19 @@ __global__ __launch_bounds__(256) void k_project(
   s.opacity = (float)o;
   s.bx0 = (int16_t)x0; s.bx1 = (int16_t)x1; s.by0 = (int16_t)y0; s.by1 = (int16_t)y1;
   s.depth_bits = __float_as_uint((float)z);
+  const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
+  const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
+  {
+    const BlockCull bc(s, tile_shift, cam.width, cam.height);
+    unsigned int live = 0u;
+    int r = 0;
+    for (int ty = ty0; ty <= ty1 && r < 32; ++ty)
+      for (int tx = tx0; tx <= tx1 && r < 32; ++tx, ++r)
+        if (bc.live(tx, ty)) live |= 1u << r;
+    s.live = live;
+  }
   out[i] = s;
-  nt = (unsigned int)(((s.bx1 >> tile_shift) - (s.bx0 >> tile_shift) + 1) *
-                      ((s.by1 >> tile_shift) - (s.by0 >> tile_shift) + 1));
+  nt = (unsigned int)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   n_tiles[i] = nt;
 }
 
@@ -262,9 +272,11 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
   const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
   const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
   unsigned int p = off[i];
+  const BlockCull bc(s, tile_shift, W, H);
+  int r = 0;
   for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx, ++p) {
-      const bool live = block_live(s, tx, ty, tile_shift, W, H);
+    for (int tx = tx0; tx <= tx1; ++tx, ++p, ++r) {
+      const bool live = pair_live(s, bc, r, tx, ty);
       tile_ids[p] = live ? (unsigned int)(ty * tiles_x + tx) : (unsigned int)n_tiles;
       keys[p] = key;
       if (!live)
@@ -301,9 +313,11 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
     if (g.bx0 > g.bx1) continue;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
+    const BlockCull bc(g, tile_shift, W, H);
+    int r = 0;
     for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (!block_live(g, tx, ty, tile_shift, W, H)) continue;
+      for (int tx = tx0; tx <= tx1; ++tx, ++r) {
+        if (!pair_live(g, bc, r, tx, ty)) continue;
         const int t = ty * tiles_x + tx;
         atomicAdd(&h[t >> 1], 1u << (16 * (t & 1)));
       }
@@ -361,9 +375,11 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
     unsigned int p = off[i];                   // Gaussian-major pair index (uplift records)
+    const BlockCull bc(g, tile_shift, W, H);
+    int r = 0;
     for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx, ++p) {
-        if (!block_live(g, tx, ty, tile_shift, W, H)) {
+      for (int tx = tx0; tx <= tx1; ++tx, ++p, ++r) {
+        if (!pair_live(g, bc, r, tx, ty)) {
           for (int l = 0; l < cull.n; ++l) {
             cull.rec[l][2ull * p] = make_float2(__int_as_float(-1), 0.0f);
             cull.rec[l][2ull * p + 1] = make_float2(__int_as_float(-1), 0.0f);

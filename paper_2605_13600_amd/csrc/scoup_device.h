@@ -29,7 +29,7 @@ struct __align__(16) GSplat {
   float l00, l10, l11, opacity;
   int16_t bx0, bx1, by0, by1;
   uint32_t depth_bits;   // float32 view depth (positive, so bits order like values)
-  uint32_t pad;
+  uint32_t live;         // reachable blocks among the first 32 of the box (see pair_live)
 };
 static_assert(sizeof(GSplat) == 48, "GSplat layout");
 
@@ -39,32 +39,42 @@ static_assert(sizeof(GSplat) == 48, "GSplat layout");
 // else the smallest of the four edge minima (each a clamped 1D quadratic).
 // Conservative: a block is dropped only if that minimum exceeds log2(255 o)
 // by a relative 1e-4 (plus 1e-4), far beyond float32 rounding of either side.
-__device__ __forceinline__ bool block_live(const GSplat& g, int bx, int by, int shift, int W, int H) {
-  const int x_lo = bx << shift, y_lo = by << shift;
-  const int x_hi = min(x_lo + (1 << shift), W) - 1, y_hi = min(y_lo + (1 << shift), H) - 1;
-  const float xa = ((float)(x_lo - g.ix) + 0.5f) - g.fx, xb = ((float)(x_hi - g.ix) + 0.5f) - g.fx;
-  const float ya = ((float)(y_lo - g.iy) + 0.5f) - g.fy, yb = ((float)(y_hi - g.iy) + 0.5f) - g.fy;
-  if (xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f) return true;
-  const float a = g.l00, b = g.l10, c = g.l11;
-  auto q = [&](float dx, float dy) {
+// The per-Gaussian constants are set up once for all blocks of its box.
+struct BlockCull {
+  int ix, iy, shift, W, H;
+  float fx, fy, a, b, c, rh, rv, thr;
+  __device__ __forceinline__ BlockCull(const GSplat& g, int shift_, int W_, int H_) {
+    ix = g.ix; iy = g.iy; fx = g.fx; fy = g.fy; shift = shift_; W = W_; H = H_;
+    a = g.l00; b = g.l10; c = g.l11;
+    rh = -b / a;                                   // horizontal edge: argmin dx = rh dy
+    rv = -a * b / fmaf(b, b, c * c);               // vertical edge: argmin dy = rv dx
+    thr = fmaf(log2f(255.0f * g.opacity), 1.0001f, 1e-4f);
+  }
+  __device__ __forceinline__ float q(float dx, float dy) const {
     const float u = fmaf(a, dx, b * dy), v = c * dy;
     return fmaf(u, u, v * v);
-  };
-  // horizontal edges dy = ya, yb: minimum at dx = -b dy / a
-  const float h0 = q(fminf(fmaxf(-b * ya / a, xa), xb), ya);
-  const float h1 = q(fminf(fmaxf(-b * yb / a, xa), xb), yb);
-  // vertical edges dx = xa, xb: minimum at dy = -a b dx / (b^2 + c^2)
-  const float den = fmaf(b, b, c * c);
-  const float v0 = q(xa, fminf(fmaxf(-a * b * xa / den, ya), yb));
-  const float v1 = q(xb, fminf(fmaxf(-a * b * xb / den, ya), yb));
-  const float qmin = fminf(fminf(h0, h1), fminf(v0, v1));
-  const float qmax = log2f(255.0f * g.opacity);
-  return qmin <= fmaf(qmax, 1.0001f, 1e-4f);
+  }
+  __device__ __forceinline__ bool live(int bx, int by) const {
+    const int x_lo = bx << shift, y_lo = by << shift;
+    const int x_hi = min(x_lo + (1 << shift), W) - 1, y_hi = min(y_lo + (1 << shift), H) - 1;
+    const float xa = ((float)(x_lo - ix) + 0.5f) - fx, xb = ((float)(x_hi - ix) + 0.5f) - fx;
+    const float ya = ((float)(y_lo - iy) + 0.5f) - fy, yb = ((float)(y_hi - iy) + 0.5f) - fy;
+    if (xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f) return true;
+    const float h0 = q(fminf(fmaxf(rh * ya, xa), xb), ya);
+    const float h1 = q(fminf(fmaxf(rh * yb, xa), xb), yb);
+    const float v0 = q(xa, fminf(fmaxf(rv * xa, ya), yb));
+    const float v1 = q(xb, fminf(fmaxf(rv * xb, ya), yb));
+    return fminf(fminf(h0, h1), fminf(v0, v1)) <= thr;
+  }
+};
+
+// Bit r of GSplat::live is set when block r (row-major in the Gaussian's
+// block box) is reachable, for the first 32 blocks; later blocks are tested
+// again where needed.
+__device__ __forceinline__ bool pair_live(const GSplat& g, const BlockCull& bc, int r, int bx, int by) {
+  return r < 32 ? ((g.live >> r) & 1u) != 0u : bc.live(bx, by);
 }
 
-// The fields of a GSplat that compositing needs, held by the lane that loaded
-// it; bcast(k) reads lane k's copy into every lane via SGPRs (v_readlane), so
-// the sequential per-Gaussian loop does not wait on LDS.
 // One batch Gaussian held by its lane, in block-relative form for the
 // compositing loop: integer centre offset from the block origin (exact in
 // float32), fraction, scaled conic factor, opacity and the largest q that

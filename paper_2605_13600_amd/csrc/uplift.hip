@@ -50,6 +50,8 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
   __shared__ float E[B * kEStride];
+  __shared__ float4 s_bs[3 * (B + 2)];        // the batch's splats, block-relative (three float4 each),
+                                              // two spare slots for the reads one step ahead
   __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
   __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
   if (st->view_overflow) return;
@@ -102,27 +104,34 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const bool all_done = __ballot(!done) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
-    BlockSplat mine;
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
-    if (j < L) {                               // every lane group holds the batch's splats
+    if (j < L) {                               // every lane group holds the batch's ids and boxes
       my_id = (unsigned int)keys[start + j];
       const GSplat gg = splats[my_id];
-      mine.load(gg, tile_x0, tile_y0);
       own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
+      if (lane < B) {                          // LDS copy read back as a broadcast in the loop
+        BlockSplat bs;
+        bs.load(gg, tile_x0, tile_y0);
+        s_bs[3 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
+        s_bs[3 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
+        s_bs[3 * lane + 2] = make_float4(bs.qmax, 0.0f, 0.0f, 0.0f);
+      }
     }
+    __syncthreads();
     unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
     if (!all_done) {
-      for (int k = 0; k < nb; ++k) {
-        const BlockSplat g = mine.bcast(k);
-        const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
-        const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
+      // one Gaussian of the batch: returns true once every pixel of the block is done
+      auto step = [&](int k, const float4& c0, const float4& c1, float cq) -> bool {
+        // c0 = (hx, hy, fx, fy), c1 = (l00, l10, l11, opacity), cq = qmax
+        const float dx = (pcx - c0.x) - c0.z, dy = (pcy - c0.y) - c0.w;
+        const float u = fmaf(c1.x, dx, c1.y * dy), v = c1.z * dy;
         const float q = fmaf(u, u, v * v);
-        const bool take = !done && q <= g.qmax;
-        if (__ballot(take) == 0ull) continue;
+        const bool take = !done && q <= cq;
+        if (__ballot(take) == 0ull) return false;
         float e = 0.0f;
         if (take) {
-          const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
+          const float alpha = fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q));
           const float testT = T * (1.0f - alpha);
           if (testT < kTMin) {
             done = true;
@@ -136,7 +145,19 @@ __global__ __launch_bounds__(64) void k_composite_blk(
           contributed |= 1ull << k;
           E[k * kEStride + lane] = e;
         }
-        if (__ballot(!done) == 0ull) break;
+        return __ballot(!done) == 0ull;
+      };
+      // two register sets alternate so that each Gaussian's splat is read
+      // from LDS one step ahead without copies
+      float4 a0 = s_bs[0], a1 = s_bs[1];
+      float aq = s_bs[2].x;
+      for (int k = 0; k < nb; k += 2) {
+        // slots past the batch hold stale data; they are never used
+        const float4 b0 = s_bs[3 * k + 3], b1 = s_bs[3 * k + 4];
+        const float bq = s_bs[3 * k + 5].x;
+        if (step(k, a0, a1, aq) || k + 1 >= nb) break;
+        a0 = s_bs[3 * k + 6]; a1 = s_bs[3 * k + 7]; aq = s_bs[3 * k + 8].x;
+        if (step(k + 1, b0, b1, bq)) break;
       }
     }
     __syncthreads();
