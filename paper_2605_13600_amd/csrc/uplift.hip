@@ -48,10 +48,10 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
-  static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
-  __shared__ float E[B * kEStride];
-  __shared__ float4 s_bs[3 * (B + 2)];        // the batch's splats, block-relative (three float4 each),
-                                              // two spare slots for the reads one step ahead
+  static_assert(B == 32, "batch of 32 Gaussians (one bit each in a lane's 32-bit queue)");
+  constexpr int ES = B + 4;                    // E row stride (16-byte aligned rows)
+  __shared__ float E[64 * ES];                 // E[pixel][k]: weight of batch Gaussian k at the pixel
+  __shared__ float4 s_bs[3 * B];               // the batch's splats, block-relative (three float4 each)
   __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
   __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
   if (st->view_overflow) return;
@@ -94,10 +94,17 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   if (L == 0) return;
   __syncthreads();
 
+  // The block's four 4x4 quadrants composite independently: each lane walks
+  // the batch Gaussians that reach its quadrant (a 32-bit queue, the same for
+  // the 16 lanes of a quadrant), so one step of the wave advances up to four
+  // Gaussians, one per quadrant, while every pixel still takes its
+  // Gaussians in depth order.
+  const int quad = ((ly >> 2) << 1) | (lx >> 2);
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = 1.0f;
   bool done = !inside;
   unsigned int count = 0u;                     // this pixel's contributions
+  float* Erow = E + lane * ES;
   const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
   const int gq0 = lane - gk;                   // first pixel of the lane's group
   for (int b0 = 0; b0 < L; b0 += B) {
@@ -106,64 +113,65 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const int nb = min(B, L - b0);
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
+    unsigned int qmask = 0u;                   // quadrants Gaussian gk can reach (lanes < B)
     if (j < L) {                               // every lane group holds the batch's ids and boxes
       my_id = (unsigned int)keys[start + j];
       const GSplat gg = splats[my_id];
       own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
-      if (lane < B) {                          // LDS copy read back as a broadcast in the loop
+      if (lane < B) {
         BlockSplat bs;
         bs.load(gg, tile_x0, tile_y0);
         s_bs[3 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
         s_bs[3 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
         s_bs[3 * lane + 2] = make_float4(bs.qmax, 0.0f, 0.0f, 0.0f);
+        const BlockCull c4(gg, 2, W, H);       // 4x4 sub-blocks of this 8x8 block
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd)
+          if (c4.live(2 * tx + (qd & 1), 2 * ty + (qd >> 1))) qmask |= 1u << qd;
       }
     }
+#pragma unroll
+    for (int c = 0; c < B; c += 4) *reinterpret_cast<float4*>(Erow + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    // the queue of this lane's quadrant: batch Gaussians (lanes < nb) reaching it
+    const unsigned int q0 = (unsigned int)__ballot(qmask & 1u), q1 = (unsigned int)__ballot(qmask & 2u);
+    const unsigned int q2 = (unsigned int)__ballot(qmask & 4u), q3 = (unsigned int)__ballot(qmask & 8u);
+    unsigned int rem = quad == 0 ? q0 : quad == 1 ? q1 : quad == 2 ? q2 : q3;
     __syncthreads();
-    unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
+    unsigned int contrib = 0u;                 // bit k: this pixel got e > 0 from Gaussian k
     if (!all_done) {
-      // one Gaussian of the batch: returns true once every pixel of the block is done
-      auto step = [&](int k, const float4& c0, const float4& c1, float cq) -> bool {
-        // c0 = (hx, hy, fx, fy), c1 = (l00, l10, l11, opacity), cq = qmax
+      while (__ballot(rem != 0u && !done) != 0ull) {
+        const bool has = rem != 0u;
+        const int k = has ? __builtin_ctz(rem) : 0;
+        rem &= rem - 1u;
+        const float4 c0 = s_bs[3 * k], c1 = s_bs[3 * k + 1];   // (hx, hy, fx, fy), (l00, l10, l11, o)
+        const float cq = s_bs[3 * k + 2].x;                    // qmax
         const float dx = (pcx - c0.x) - c0.z, dy = (pcy - c0.y) - c0.w;
         const float u = fmaf(c1.x, dx, c1.y * dy), v = c1.z * dy;
         const float q = fmaf(u, u, v * v);
-        const bool take = !done && q <= cq;
-        if (__ballot(take) == 0ull) return false;
-        float e = 0.0f;
+        const bool take = has && !done && q <= cq;
+        if (__ballot(take) == 0ull) continue;
         if (take) {
           const float alpha = fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q));
           const float testT = T * (1.0f - alpha);
           if (testT < kTMin) {
             done = true;
           } else {
-            e = alpha * T;
+            Erow[k] = alpha * T;
+            contrib |= 1u << k;
+            ++count;
             T = testT;
           }
         }
-        count += e > 0.0f ? 1u : 0u;
-        if (__ballot(e > 0.0f)) {
-          contributed |= 1ull << k;
-          E[k * kEStride + lane] = e;
-        }
-        return __ballot(!done) == 0ull;
-      };
-      // two register sets alternate so that each Gaussian's splat is read
-      // from LDS one step ahead without copies
-      float4 a0 = s_bs[0], a1 = s_bs[1];
-      float aq = s_bs[2].x;
-      for (int k = 0; k < nb; k += 2) {
-        // slots past the batch hold stale data; they are never used
-        const float4 b0 = s_bs[3 * k + 3], b1 = s_bs[3 * k + 4];
-        const float bq = s_bs[3 * k + 5].x;
-        if (step(k, a0, a1, aq) || k + 1 >= nb) break;
-        a0 = s_bs[3 * k + 6]; a1 = s_bs[3 * k + 7]; aq = s_bs[3 * k + 8].x;
-        if (step(k + 1, b0, b1, bq)) break;
       }
     }
+    // Gaussians with a contribution anywhere in the block
+    unsigned int cw = contrib;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cw |= (unsigned int)__shfl_xor((int)cw, o, 64);
+    const unsigned long long contributed = cw;
     __syncthreads();
     // every pair's two record slots per level are written, zero weight included
     const bool had = gk < nb && ((contributed >> gk) & 1ull);
-    const float* row = E + gk * kEStride + gq0;
     const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
 #pragma unroll
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -173,7 +181,7 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         const unsigned long long m0 = s_mask[l][0] >> gq0, m1 = s_mask[l][1] >> gq0;
 #pragma unroll 8
         for (int q = 0; q < B; ++q) {
-          const float x = row[q];
+          const float x = E[(gq0 + q) * ES + gk];
           if ((m0 >> q) & 1ull) w0 += x;
           else if ((m1 >> q) & 1ull) w1 += x;
         }
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         while (km) {
           const int k = __ffsll((long long)km) - 1;
           km &= km - 1;
-          const float e = E[k * kEStride + lane];
+          const float e = Erow[k];
           const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
           unsigned long long rm = __ballot(third && e > 0.0f);
           while (rm) {
@@ -289,12 +297,13 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 }
 
 // ---------------------------------------------------------------------------
-// row build: G (a power of two <= 16) consecutive Gaussians per workgroup;
-// lane l of wave w owns Gaussian i0 + l % G and walks views
-// w (64/G) + l / G, stepping by 4 (64/G), so 64/G views per wave are in flight;
-// rows (stride M+1) in LDS take the code of each record with LDS atomic adds;
-// no barriers between views.  Rows are written back coalesced, Top-K and
-// entropy read from LDS.
+// row build: G (a power of two <= 16) consecutive Gaussians per workgroup,
+// their rows (stride M+1) in LDS; wave w walks views w, w+4, ...  The
+// records of the G Gaussians in one view are one contiguous range
+// (Gaussian-major), so the wave reads it 64 records at a time, coalesced; each
+// lane finds its record's Gaussian from the range bounds held by lanes 0..G
+// and adds the record's code with LDS atomic adds.  Rows are written back
+// coalesced, Top-K and entropy read from LDS.
 // ---------------------------------------------------------------------------
 template <int NS>
 __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
@@ -303,36 +312,47 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   const long long i0 = (long long)blockIdx.x * G;
   const int gn = (int)min((long long)G, a.n - i0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int VL = 64 / G;                     // views per wave in flight
-  const int g = lane % G, vsub = lane / G;
   float* acc = a.acc + i0 * M;
   for (int j = tid; j < gn * M; j += 256) rows[(j / M) * stride + (j % M)] = acc[j];
   __syncthreads();
   const unsigned int cap = (unsigned int)a.capacity;
-  if (g < gn) {
-    float* row = rows + g * stride;
-    for (int v = wave * VL + vsub; v < a.n_views; v += 4 * VL) {
-      const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0 + g;
-      const unsigned int lo = min(offv[0], cap), hi = min(offv[1], cap);
-      const float2* recv = a.records + (long long)v * 2 * a.capacity;
-      for (unsigned int r = 2 * lo; r < 2 * hi; ++r) {
-        const float2 rc = recv[r];
-        const int reg = __float_as_int(rc.x);
-        if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
-        const long long gr = (long long)reg * a.k_code;
-        for (int c = 0; c < a.k_code; c += 4) {     // issue four slots' loads before their adds
-          int jj[4];
-          float cv[4];
+  const bool vec = (a.k_code & 3) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(a.code_idx) | reinterpret_cast<uintptr_t>(a.code_val)) & 15) == 0;
+  for (int v = wave; v < a.n_views; v += 4) {
+    const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0;
+    const unsigned int ob = lane <= gn ? 2u * min(offv[lane], cap) : 0u;   // first record of Gaussian lane
+    const unsigned int r0 = (unsigned int)__builtin_amdgcn_readlane((int)ob, 0);
+    const unsigned int r1 = (unsigned int)__builtin_amdgcn_readlane((int)ob, gn);
+    const float2* recv = a.records + (long long)v * 2 * a.capacity;
+    for (unsigned int base = r0; base < r1; base += 64) {
+      const unsigned int r = base + (unsigned int)lane;
+      int g = 0;                               // last Gaussian whose range starts at or before r
+      for (int t = 1; t < gn; ++t) g = r >= (unsigned int)__builtin_amdgcn_readlane((int)ob, t) ? t : g;
+      if (r >= r1) continue;
+      const float2 rc = recv[r];
+      const int reg = __float_as_int(rc.x);
+      if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
+      float* row = rows + g * stride;
+      const long long gr = (long long)reg * a.k_code;
+      for (int c = 0; c < a.k_code; c += 4) {     // four slots' loads before their adds
+        int jj[4];
+        float cv[4];
+        if (vec) {
+          const int4 ji = *reinterpret_cast<const int4*>(a.code_idx + gr + c);
+          const float4 jv = *reinterpret_cast<const float4*>(a.code_val + gr + c);
+          jj[0] = ji.x; jj[1] = ji.y; jj[2] = ji.z; jj[3] = ji.w;
+          cv[0] = jv.x; cv[1] = jv.y; cv[2] = jv.z; cv[3] = jv.w;
+        } else {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             jj[u] = c + u < a.k_code ? a.code_idx[gr + c + u] : -1;
             cv[u] = c + u < a.k_code ? a.code_val[gr + c + u] : 0.0f;
           }
+        }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
-            else if (jj[u] >= 0) atomicAdd(&row[jj[u]], rc.y * cv[u]);
-          }
+        for (int u = 0; u < 4; ++u) {
+          if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
+          else if (jj[u] >= 0) atomicAdd(&row[jj[u]], rc.y * cv[u]);
         }
       }
     }
@@ -482,9 +502,8 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Gaussians per row-build workgroup: a power of two (lanes split into
-// Gaussians x views), rows within 64 KB of LDS, at most 16 so that four or
-// more views per wave are in flight
+// Gaussians per row-build workgroup: a power of two, at most 16 (rows of at
+// most 64 KB of LDS, small enough for several workgroups per CU)
 int rowbuild_group(int m) {
   int g = 16;
   while (g > 1 && g * (m + 1) > 16384) g >>= 1;
