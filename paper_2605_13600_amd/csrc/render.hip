@@ -66,7 +66,15 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
     if (__ballot(!done) == 0ull) break;
     const int nb = min(kRenderBatch, L - b0);
     BlockSplat mine;
-    if (lane < nb) mine.load(splats[(unsigned int)keys[start + b0 + lane]], tile_x0, tile_y0);
+    bool reach = false;                        // Gaussian `lane` reaches this wave's two pixel rows
+    if (lane < nb) {
+      const GSplat gs = splats[(unsigned int)keys[start + b0 + lane]];
+      mine.load(gs, tile_x0, tile_y0);
+      const BlockCull bc(gs, 3, W, H);
+      const int ry = tile_y0 + 2 * wave;
+      reach = ry < H && bc.live_rect(tile_x0, min(tile_x0 + 8, W) - 1, ry, min(ry + 2, H) - 1);
+    }
+    unsigned long long queue = __ballot(reach);
     for (int t = lane; t < nb * K; t += 64) {
       const int k = t / K, j = t - k * K;
       const long long id = (long long)(unsigned int)keys[start + b0 + k];
@@ -74,7 +82,9 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
       tv[t] = topk_val[id * K + j];
     }
     render_wave_lds_sync();
-    for (int k = 0; k < nb; ++k) {
+    while (queue) {                            // only the batch Gaussians that reach these rows
+      const int k = __ffsll((long long)queue) - 1;
+      queue &= queue - 1ull;
       const BlockSplat g = mine.bcast(k);
       const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;

@@ -56,7 +56,10 @@ struct BlockCull {
   }
   __device__ __forceinline__ bool live(int bx, int by) const {
     const int x_lo = bx << shift, y_lo = by << shift;
-    const int x_hi = min(x_lo + (1 << shift), W) - 1, y_hi = min(y_lo + (1 << shift), H) - 1;
+    return live_rect(x_lo, min(x_lo + (1 << shift), W) - 1, y_lo, min(y_lo + (1 << shift), H) - 1);
+  }
+  // the same test on the pixel rectangle [x_lo, x_hi] x [y_lo, y_hi] (inclusive)
+  __device__ __forceinline__ bool live_rect(int x_lo, int x_hi, int y_lo, int y_hi) const {
     const float xa = ((float)(x_lo - ix) + 0.5f) - fx, xb = ((float)(x_hi - ix) + 0.5f) - fx;
     const float ya = ((float)(y_lo - iy) + 0.5f) - fy, yb = ((float)(y_hi - iy) + 0.5f) - fy;
     if (xa <= 0.0f && xb >= 0.0f && ya <= 0.0f && yb >= 0.0f) return true;
