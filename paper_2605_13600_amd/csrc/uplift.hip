@@ -26,17 +26,21 @@ namespace scoup {
 
 
 // ---------------------------------------------------------------------------
-// composite + per-(Gaussian, block, region) weights: one 8x8 pixel block per
+// composite + per-(Gaussian, block, region) reduction: one 8x8 pixel block per
 // workgroup (one wave), lane l = pixel (l & 7, l >> 3) of the block, the
-// block's list in depth order (binning), taken in batches of B Gaussians.
-// Every weight e > 0 is added at once (LDS atomic add) to the batch
-// Gaussian's sum for the pixel's record region (the block's first two
-// regions per level); after the batch, lane k writes Gaussian k's two
-// records.  Pixels of a third or further region in the block (rare) are
-// reduced across the wave and added to the accumulator directly.
+// block's list already in depth order (binning).
+// Per batch of B depth-ordered Gaussians the wave writes every lane's weight
+// e into an LDS matrix E[Gaussian][pixel]; afterwards lane g B + k sums row k
+// over the pixels [g B, g B + B) of the block's two record regions (a
+// transposed reduction: no cross-lane traffic inside the sequential
+// compositing loop), the 64 / B partial sums are combined across lane groups
+// and the pair's two records are written.  Pixels of a third or further
+// region in the block (rare) are reduced across the wave and added to the
+// accumulator directly.  B trades LDS (B x 65 floats, which sets occupancy)
+// against the per-batch overhead.
 // ---------------------------------------------------------------------------
-constexpr int kEStride = 2;                   // record sums per (level, batch Gaussian)
-constexpr int kCompositeBatch = 64;
+constexpr int kEStride = 65;
+constexpr int kCompositeBatch = 32;
 
 template <int B>
 __global__ __launch_bounds__(64) void k_composite_blk(
@@ -44,11 +48,12 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
-  static_assert(B == 32 || B == 64, "batch of 32 or 64 Gaussians");
-  __shared__ float s_w[kMaxLevels][B][kEStride];   // the batch's record sums
+  static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
+  __shared__ float E[B * kEStride];
   __shared__ float4 s_bs[3 * (B + 2)];        // the batch's splats, block-relative (three float4 each),
                                               // two spare slots for the reads one step ahead
-  __shared__ float s_rg[kMaxLevels][2];       // the record regions' global ids (int bits; -1: none)
+  __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
+  __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
   if (st->view_overflow) return;
   const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -61,9 +66,9 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   const bool inside = px < W && py < H;
   // per level: the pixel's region (validated on every pixel, empty blocks
   // included) and the block's two record regions r0 = region of the first
-  // pixel with one, r1 = first other region; slot 0 / 1 for those, 2 for a
-  // further region, 3 for none (two bits per level)
-  unsigned int slots = 0u, has2 = 0u;
+  // pixel with one, r1 = first other region; pixels of further regions are
+  // flagged (has2) and handled after each batch
+  unsigned int has2 = 0u;                      // bit l: level l has pixels of a third region
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l) {
     if (l >= n_levels) break;
@@ -77,41 +82,44 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
     const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
     const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
-    const unsigned int slot = reg < 0 ? 3u : reg == r0 ? 0u : reg == r1 ? 1u : 2u;
-    slots |= slot << (2 * l);
-    if (__ballot(slot == 2u)) has2 |= 1u << l;
+    const unsigned long long m0 = __ballot(reg >= 0 && reg == r0);
+    const unsigned long long m1 = __ballot(reg >= 0 && reg == r1);
+    if (__ballot(reg >= 0 && reg != r0 && reg != r1)) has2 |= 1u << l;
     if (lane == 0) {
+      s_mask[l][0] = m0; s_mask[l][1] = m1;
       s_rg[l][0] = __int_as_float(r0 >= 0 ? (int)(lv.region_base + r0) : -1);
       s_rg[l][1] = __int_as_float(r1 >= 0 ? (int)(lv.region_base + r1) : -1);
     }
   }
   if (L == 0) return;
+  __syncthreads();
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = 1.0f;
   bool done = !inside;
   unsigned int count = 0u;                     // this pixel's contributions
+  const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
+  const int gq0 = lane - gk;                   // first pixel of the lane's group
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(!done) == 0ull;
-    const int j = b0 + lane;
+    const int j = b0 + gk;
     const int nb = min(B, L - b0);
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
-    if (lane < nb) {
+    if (j < L) {                               // every lane group holds the batch's ids and boxes
       my_id = (unsigned int)keys[start + j];
       const GSplat gg = splats[my_id];
       own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
-      BlockSplat bs;
-      bs.load(gg, tile_x0, tile_y0);
-      s_bs[3 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
-      s_bs[3 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
-      s_bs[3 * lane + 2] = make_float4(bs.qmax, 0.0f, 0.0f, 0.0f);
-    }
-    if (lane < B) {
-#pragma unroll
-      for (int l = 0; l < kMaxLevels; ++l) { s_w[l][lane][0] = 0.0f; s_w[l][lane][1] = 0.0f; }
+      if (lane < B) {                          // LDS copy read back as a broadcast in the loop
+        BlockSplat bs;
+        bs.load(gg, tile_x0, tile_y0);
+        s_bs[3 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
+        s_bs[3 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
+        s_bs[3 * lane + 2] = make_float4(bs.qmax, 0.0f, 0.0f, 0.0f);
+      }
     }
     __syncthreads();
+    unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
     if (!all_done) {
       // one Gaussian of the batch: returns true once every pixel of the block is done
       auto step = [&](int k, const float4& c0, const float4& c1, float cq) -> bool {
@@ -130,50 +138,12 @@ __global__ __launch_bounds__(64) void k_composite_blk(
           } else {
             e = alpha * T;
             T = testT;
-            ++count;
-#pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-              if (l >= n_levels) break;
-              const unsigned int sl = (slots >> (2 * l)) & 3u;
-              if (sl < 2u) atomicAdd(&s_w[l][k][sl], e);
-            }
           }
         }
-        if (has2) {   // third and further regions of the block: straight to the accumulator
-          const unsigned long long cm = __ballot(e > 0.0f);
-          if (cm) {
-            const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
-#pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-              if (l >= n_levels || !((has2 >> l) & 1u)) continue;
-              const LevelView& lv = args.lv[l];
-              const bool third = ((slots >> (2 * l)) & 3u) == 2u;
-              unsigned long long rm = __ballot(third && e > 0.0f);
-              if (!rm) continue;
-              const int reg = inside ? lv.rmap[(long long)py * W + px] : -1;
-              while (rm) {
-                const int l0 = __ffsll((long long)rm) - 1;
-                const int rr = __builtin_amdgcn_readlane(reg, l0);
-                const unsigned long long same = __ballot(reg == rr) & rm;
-                const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
-                if (lv.dense_F) {      // dense feature uplift: w F_r and w
-                  const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
-                  const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
-                  for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
-                  if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
-                } else {
-                  const unsigned long long arow = (unsigned long long)idk * (unsigned long long)m_atoms;
-                  const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
-                  for (int c = lane; c < lv.k_code; c += 64) {
-                    const int jj = lv.code_idx[gr + c];
-                    if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                    else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
-                  }
-                }
-                rm &= ~same;
-              }
-            }
-          }
+        count += e > 0.0f ? 1u : 0u;
+        if (__ballot(e > 0.0f)) {
+          contributed |= 1ull << k;
+          E[k * kEStride + lane] = e;
         }
         return __ballot(!done) == 0ull;
       };
@@ -192,15 +162,72 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     }
     __syncthreads();
     // every pair's two record slots per level are written, zero weight included
-    if (lane < nb) {
-      const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
-      const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+    const bool had = gk < nb && ((contributed >> gk) & 1ull);
+    const float* row = E + gk * kEStride + gq0;
+    const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
+#pragma unroll
+    for (int l = 0; l < kMaxLevels; ++l) {
+      if (l >= n_levels) break;
+      float w0 = 0.0f, w1 = 0.0f;
+      if (had) {
+        const unsigned long long m0 = s_mask[l][0] >> gq0, m1 = s_mask[l][1] >> gq0;
+#pragma unroll 8
+        for (int q = 0; q < B; ++q) {
+          const float x = row[q];
+          if ((m0 >> q) & 1ull) w0 += x;
+          else if ((m1 >> q) & 1ull) w1 += x;
+        }
+      }
+#pragma unroll
+      for (int o = B; o < 64; o <<= 1) {       // combine the lane groups
+        w0 += __shfl_xor(w0, o, 64);
+        w1 += __shfl_xor(w1, o, 64);
+      }
+      if (lane < nb) {
+        const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+        float2* rec = args.lv[l].records;
+        rec[2ull * p] = make_float2(s_rg[l][0], w0);
+        rec[2ull * p + 1] = make_float2(s_rg[l][1], w1);
+      }
+    }
+    if (has2 && contributed) {   // third and further regions of the block: straight to the accumulator
 #pragma unroll
       for (int l = 0; l < kMaxLevels; ++l) {
-        if (l >= n_levels) break;
-        float2* rec = args.lv[l].records;
-        rec[2ull * p] = make_float2(s_rg[l][0], s_w[l][lane][0]);
-        rec[2ull * p + 1] = make_float2(s_rg[l][1], s_w[l][lane][1]);
+        if (l >= n_levels || !((has2 >> l) & 1u)) continue;
+        const LevelView& lv = args.lv[l];
+        const int reg = inside ? lv.rmap[(long long)py * W + px] : -1;
+        const int r0 = __float_as_int(s_rg[l][0]), r1 = __float_as_int(s_rg[l][1]);
+        const int greg = reg >= 0 && reg < lv.n_regions ? (int)(lv.region_base + reg) : -1;
+        const bool third = greg >= 0 && greg != r0 && greg != r1;
+        unsigned long long km = contributed;
+        while (km) {
+          const int k = __ffsll((long long)km) - 1;
+          km &= km - 1;
+          const float e = E[k * kEStride + lane];
+          const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
+          unsigned long long rm = __ballot(third && e > 0.0f);
+          while (rm) {
+            const int l0 = __ffsll((long long)rm) - 1;
+            const int rr = __builtin_amdgcn_readlane(reg, l0);
+            const unsigned long long same = __ballot(reg == rr) & rm;
+            const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
+            if (lv.dense_F) {      // dense feature uplift: w F_r and w
+              const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
+              const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
+              for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
+              if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
+            } else {
+              const unsigned long long arow = (unsigned long long)idk * (unsigned long long)m_atoms;
+              const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
+              for (int c = lane; c < lv.k_code; c += 64) {
+                const int jj = lv.code_idx[gr + c];
+                if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+                else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+              }
+            }
+            rm &= ~same;
+          }
+        }
       }
     }
     __syncthreads();
@@ -266,14 +293,13 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 // their rows (stride M+1) in LDS; wave w walks views w, w+4, ...  The
 // records of the G Gaussians in one view are one contiguous range
 // (Gaussian-major), so the wave reads it 64 records at a time, coalesced; each
-// lane finds its record's Gaussian by a binary search over the range bounds
-// (in LDS) and adds the record's code with LDS atomic adds.  Rows are written back
+// lane finds its record's Gaussian from the range bounds held by lanes 0..G
+// and adds the record's code with LDS atomic adds.  Rows are written back
 // coalesced, Top-K and entropy read from LDS.
 // ---------------------------------------------------------------------------
 template <int NS>
 __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   extern __shared__ float rows[];            // G * (M+1)
-  __shared__ unsigned int s_ob[4][17];       // per wave: first record of each Gaussian (+ end)
   const int M = a.m_atoms, stride = M + 1;
   const long long i0 = (long long)blockIdx.x * G;
   const int gn = (int)min((long long)G, a.n - i0);
@@ -282,26 +308,19 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   for (int j = tid; j < gn * M; j += 256) rows[(j / M) * stride + (j % M)] = acc[j];
   __syncthreads();
   const unsigned int cap = (unsigned int)a.capacity;
-  unsigned int* ob_w = s_ob[wave];
   const bool vec = (a.k_code & 3) == 0 &&
                    ((reinterpret_cast<uintptr_t>(a.code_idx) | reinterpret_cast<uintptr_t>(a.code_val)) & 15) == 0;
   for (int v = wave; v < a.n_views; v += 4) {
     const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0;
     const unsigned int ob = lane <= gn ? 2u * min(offv[lane], cap) : 0u;   // first record of Gaussian lane
-    if (lane <= gn) ob_w[lane] = ob;
     const unsigned int r0 = (unsigned int)__builtin_amdgcn_readlane((int)ob, 0);
     const unsigned int r1 = (unsigned int)__builtin_amdgcn_readlane((int)ob, gn);
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's ob_w writes before its reads
     const float2* recv = a.records + (long long)v * 2 * a.capacity;
     for (unsigned int base = r0; base < r1; base += 64) {
       const unsigned int r = base + (unsigned int)lane;
+      int g = 0;                               // last Gaussian whose range starts at or before r
+      for (int t = 1; t < gn; ++t) g = r >= (unsigned int)__builtin_amdgcn_readlane((int)ob, t) ? t : g;
       if (r >= r1) continue;
-      int lo = 0, hi = gn;                     // ob[lo] <= r < ob[hi]: the record's Gaussian is the last such lo
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (ob_w[mid] <= r) lo = mid; else hi = mid;
-      }
-      const int g = lo;
       const float2 rc = recv[r];
       const int reg = __float_as_int(rc.x);
       if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
