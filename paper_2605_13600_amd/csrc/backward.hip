@@ -49,11 +49,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   __syncthreads();
 
   const float* myrow = rows + lane * stride;
-  float T = 1.0f;
-  bool done = !inside;
+  float T = inside ? 1.0f : -1.0f;             // transmittance, negated once the pixel is finished
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   for (int b0 = 0; b0 < L; b0 += 64) {
-    if (__ballot(!done) == 0ull) break;
+    if (__ballot(T > 0.0f) == 0ull) break;
     const int j = b0 + lane;
     BlockSplat mine;
     if (j < L) {
@@ -69,20 +68,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(
       const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
       const float q = fmaf(u, u, v * v);
-      const bool take = !done && q <= g.qmax;
-      if (__ballot(take) == 0ull) continue;
-      float e = 0.0f;
-      if (take) {
-        const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
-        const float testT = T * (1.0f - alpha);
-        if (testT < kTMin) {
-          done = true;
-        } else {
-          e = alpha * T;
-          T = testT;
-        }
-      }
-      if (__ballot(e > 0.0f)) {
+      // branchless front-to-back step; T < 0 marks a finished pixel
+      const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
+      const float testT = T * (1.0f - alpha);
+      const bool take = T > 0.0f && q <= g.qmax;
+      const bool keep = take && testT >= kTMin;
+      const float e = keep ? alpha * T : 0.0f;
+      T = take ? (keep ? testT : -T) : T;
+      if (__ballot(keep)) {
         float gsum = 0.0f;
         for (int kk = 0; kk < K; ++kk) {
           const int jj = s_ti[k * K + kk];
@@ -92,7 +85,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(
         }
         if (lane < K && gsum != 0.0f) atomic_add_f32(&grad_val[(long long)s_id[k] * K + lane], gsum);
       }
-      if (__ballot(!done) == 0ull) break;
+      if (__ballot(T > 0.0f) == 0ull) break;
     }
     __syncthreads();
   }

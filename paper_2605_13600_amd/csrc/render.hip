@@ -58,12 +58,11 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
   float* myrow = rows + pix * stride;
   int* ti = s_ti[wave];
   float* tv = s_tv[wave];
-  float T = 1.0f;
-  bool done = !inside;
+  float T = inside ? 1.0f : -1.0f;             // transmittance, negated once the pixel is finished
   unsigned int count = 0u;
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   for (int b0 = 0; b0 < L; b0 += kRenderBatch) {
-    if (__ballot(!done) == 0ull) break;
+    if (__ballot(T > 0.0f) == 0ull) break;
     const int nb = min(kRenderBatch, L - b0);
     BlockSplat mine;
     bool reach = false;                        // Gaussian `lane` reaches this wave's two pixel rows
@@ -89,20 +88,14 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
       const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
       const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
       const float q = fmaf(u, u, v * v);
-      const bool take = !done && q <= g.qmax;
-      if (__ballot(take) == 0ull) continue;
-      float e = 0.0f;
-      if (take) {
-        const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
-        const float testT = T * (1.0f - alpha);
-        if (testT < kTMin) {
-          done = true;
-        } else {
-          e = alpha * T;
-          T = testT;
-        }
-      }
-      if (e > 0.0f) {
+      // branchless front-to-back step; a finished pixel keeps -T (its final transmittance, negated)
+      const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
+      const float testT = T * (1.0f - alpha);
+      const bool take = T > 0.0f && q <= g.qmax;
+      const bool keep = take && testT >= kTMin;
+      const float e = keep ? alpha * T : 0.0f;
+      T = take ? (keep ? testT : -T) : T;
+      if (keep) {
         count += sub == 0 ? 1u : 0u;
         for (int kk = sub; kk < K; kk += 4) {   // fire-and-forget LDS adds: no read-modify-write chain
           const int jj = ti[k * K + kk];
@@ -110,11 +103,11 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
           else if (jj >= M) atomicOr(&st->data_error, 4u);
         }
       }
-      if (__ballot(!done) == 0ull) break;
+      if (__ballot(T > 0.0f) == 0ull) break;
     }
     render_wave_lds_sync();
   }
-  if (inside && sub == 0 && t_final) t_final[(long long)py * W + px] = T;
+  if (inside && sub == 0 && t_final) t_final[(long long)py * W + px] = fabsf(T);
   unsigned long long total = count;
   for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
   if (lane == 0 && total) atomicAdd(&st->contrib, total);

@@ -95,13 +95,12 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   __syncthreads();
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
-  float T = 1.0f;
-  bool done = !inside;
+  float T = inside ? 1.0f : -1.0f;             // transmittance; negative once the pixel is finished
   unsigned int count = 0u;                     // this pixel's contributions
   const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
   const int gq0 = lane - gk;                   // first pixel of the lane's group
   for (int b0 = 0; b0 < L; b0 += B) {
-    const bool all_done = __ballot(!done) == 0ull;
+    const bool all_done = __ballot(T > 0.0f) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
     unsigned int my_id = 0;
@@ -119,33 +118,22 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       }
     }
     __syncthreads();
-    unsigned long long contributed = 0ull;     // bit k: Gaussian k of the batch has e > 0
+    unsigned int contrib = 0u;                 // bit k: this pixel got e > 0 from batch Gaussian k
     if (!all_done) {
-      // one Gaussian of the batch: returns true once every pixel of the block is done
-      auto step = [&](int k, const float4& c0, const float4& c1, float cq) -> bool {
+      // one Gaussian of the batch, without branches: T < 0 marks a finished pixel
+      auto step = [&](int k, const float4& c0, const float4& c1, float cq) {
         // c0 = (hx, hy, fx, fy), c1 = (l00, l10, l11, opacity), cq = qmax
         const float dx = (pcx - c0.x) - c0.z, dy = (pcy - c0.y) - c0.w;
         const float u = fmaf(c1.x, dx, c1.y * dy), v = c1.z * dy;
         const float q = fmaf(u, u, v * v);
-        const bool take = !done && q <= cq;
-        if (__ballot(take) == 0ull) return false;
-        float e = 0.0f;
-        if (take) {
-          const float alpha = fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q));
-          const float testT = T * (1.0f - alpha);
-          if (testT < kTMin) {
-            done = true;
-          } else {
-            e = alpha * T;
-            T = testT;
-          }
-        }
-        count += e > 0.0f ? 1u : 0u;
-        if (__ballot(e > 0.0f)) {
-          contributed |= 1ull << k;
-          E[k * kEStride + lane] = e;
-        }
-        return __ballot(!done) == 0ull;
+        const float alpha = fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q));
+        const float testT = T * (1.0f - alpha);
+        const bool take = T > 0.0f && q <= cq;
+        const bool keep = take && testT >= kTMin;
+        E[k * kEStride + lane] = keep ? alpha * T : 0.0f;
+        T = take ? (keep ? testT : -1.0f) : T;
+        contrib |= (keep ? 1u : 0u) << k;
+        count += keep ? 1u : 0u;
       };
       // two register sets alternate so that each Gaussian's splat is read
       // from LDS one step ahead without copies
@@ -155,11 +143,17 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         // slots past the batch hold stale data; they are never used
         const float4 b0 = s_bs[3 * k + 3], b1 = s_bs[3 * k + 4];
         const float bq = s_bs[3 * k + 5].x;
-        if (step(k, a0, a1, aq) || k + 1 >= nb) break;
+        step(k, a0, a1, aq);
+        if (k + 1 >= nb) break;
         a0 = s_bs[3 * k + 6]; a1 = s_bs[3 * k + 7]; aq = s_bs[3 * k + 8].x;
-        if (step(k + 1, b0, b1, bq)) break;
+        step(k + 1, b0, b1, bq);
+        if (__ballot(T > 0.0f) == 0ull) break;
       }
     }
+    unsigned int cw = contrib;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cw |= (unsigned int)__shfl_xor((int)cw, o, 64);
+    const unsigned long long contributed = cw;
     __syncthreads();
     // every pair's two record slots per level are written, zero weight included
     const bool had = gk < nb && ((contributed >> gk) & 1ull);
