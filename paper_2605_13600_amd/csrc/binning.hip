@@ -626,13 +626,11 @@ int radix_passes(int n_tiles) {
 long long radix_blocks(long long capacity) { return (capacity + kRadixBlock - 1) / kRadixBlock; }
 long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
 
-// Processing order of the tiles for the compositing kernels: a counting sort
-// by descending list length (lists of 2047 or more pairs share the first
-// bucket), then the longest blocks spread out to every kOrderStride-th launch
-// slot.  A block's compositing loop is one sequential chain as long as its
-// list, so the longest lists set the launch's critical path: they start at
-// the beginning, each sharing its SIMD with shorter blocks, and run at a
-// raised wave priority (see raise_priority_for_slot).  One workgroup.
+// Processing order of the tiles for the compositing kernels: longest list
+// first (lists of 2047 or more pairs share the first bucket), so that the
+// blocks with the longest sequential loops start at the beginning of the
+// launch instead of setting its tail.  One workgroup; a counting sort on the
+// clamped length.
 constexpr int kOrderBuckets = 2048;
 
 __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restrict__ tile_start, int n_tiles,
@@ -667,17 +665,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restr
   h[2 * tid] = before;
   h[2 * tid + 1] = before + c0;
   __syncthreads();
-  // rank r (0 = longest) -> launch slot: the longest ceil(n / S) blocks take
-  // every S-th slot, the others fill the slots in between in rank order, so
-  // that each SIMD holds about one long block among shorter ones
-  const unsigned int nl = (unsigned int)(n_tiles + kOrderStride - 1) / kOrderStride;
-  for (int t = tid; t < n_tiles; t += 1024) {
-    const unsigned int r = atomicAdd(&h[bucket(t)], 1u);
-    const unsigned int sr = r - nl;
-    const unsigned int slot = r < nl ? r * kOrderStride
-                                     : (sr / (kOrderStride - 1)) * kOrderStride + 1 + sr % (kOrderStride - 1);
-    order[slot] = (unsigned int)t;
-  }
+  for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[bucket(t)], 1u)] = (unsigned int)t;
 }
 
 static CullRecords cull_of(const BinArgs& a) {

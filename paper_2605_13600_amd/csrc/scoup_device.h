@@ -100,14 +100,14 @@ struct BlockSplat {
   }
 };
 
-// Launch slots of the compositing kernels (tiles ordered by binning): every
-// kOrderStride-th slot holds one of the longest block lists, which set the
-// critical path; their waves get the highest issue priority on the SIMD they
-// share with the shorter blocks in between.
-constexpr int kOrderStride = 4;
-__device__ __forceinline__ void raise_priority_for_slot(unsigned int slot, unsigned int n_tiles) {
-  const unsigned int nl = (n_tiles + kOrderStride - 1) / kOrderStride;
-  if (slot % kOrderStride == 0 && slot / kOrderStride < nl) __builtin_amdgcn_s_setprio(3);
+// A block's compositing loop is a sequential chain as long as its Gaussian
+// list, so the longest lists set a kernel's critical path.  Their waves get a
+// higher issue priority on the SIMD they share with shorter blocks (the
+// tiles are also launched longest first).
+__device__ __forceinline__ void raise_priority_for_list(int L) {
+  if (L > 1024) __builtin_amdgcn_s_setprio(3);
+  else if (L > 512) __builtin_amdgcn_s_setprio(2);
+  else if (L > 256) __builtin_amdgcn_s_setprio(1);
 }
 
 // Small per-call status block in the workspace.
