@@ -33,7 +33,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
   if (L == 0) return;
-  raise_priority_for_list(L);
   const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
   const int tile_x0 = tx * 8, tile_y0 = ty * 8;

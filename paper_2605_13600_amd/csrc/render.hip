@@ -44,7 +44,6 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
-  raise_priority_for_list(L);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int pix = wave * 16 + (lane & 15), sub = lane >> 4;
   const int lx = pix & 7, ly = pix >> 3;

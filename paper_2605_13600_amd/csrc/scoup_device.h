@@ -100,16 +100,6 @@ struct BlockSplat {
   }
 };
 
-// A block's compositing loop is a sequential chain as long as its Gaussian
-// list, so the longest lists set a kernel's critical path.  Their waves get a
-// higher issue priority on the SIMD they share with shorter blocks (the
-// tiles are also launched longest first).
-__device__ __forceinline__ void raise_priority_for_list(int L) {
-  if (L > 1024) __builtin_amdgcn_s_setprio(3);
-  else if (L > 512) __builtin_amdgcn_s_setprio(2);
-  else if (L > 256) __builtin_amdgcn_s_setprio(1);
-}
-
 // Small per-call status block in the workspace.
 struct Status {
   unsigned int total_pairs;     // pairs of the current view

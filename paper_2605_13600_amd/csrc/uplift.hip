@@ -92,7 +92,6 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     }
   }
   if (L == 0) return;
-  raise_priority_for_list(L);
   __syncthreads();
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
