@@ -99,15 +99,24 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   unsigned int count = 0u;                     // this pixel's contributions
   const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
   const int gq0 = lane - gk;                   // first pixel of the lane's group
+  // the batch's ids and splats arrive ahead of use: the ids two batches
+  // ahead and the splats one batch ahead are loaded while a batch composites
+  unsigned long long key_cur = gk < L ? keys[start + gk] : 0ull;
+  unsigned long long key_next = B + gk < L ? keys[start + B + gk] : 0ull;
+  GSplat sp_cur;
+  if (gk < L) sp_cur = splats[(unsigned int)key_cur];
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(T > 0.0f) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
+    GSplat sp_next;
+    if (j + B < L) sp_next = splats[(unsigned int)key_next];
+    const unsigned long long key_after = j + 2 * B < L ? keys[start + j + 2 * B] : 0ull;
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
     if (j < L) {                               // every lane group holds the batch's ids and boxes
-      my_id = (unsigned int)keys[start + j];
-      const GSplat gg = splats[my_id];
+      my_id = (unsigned int)key_cur;
+      const GSplat gg = sp_cur;
       own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
       if (lane < B) {                          // LDS copy read back as a broadcast in the loop
         BlockSplat bs;
@@ -192,38 +201,62 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         const int reg = inside ? lv.rmap[(long long)py * W + px] : -1;
         const int r0 = __float_as_int(s_rg[l][0]), r1 = __float_as_int(s_rg[l][1]);
         const int greg = reg >= 0 && reg < lv.n_regions ? (int)(lv.region_base + reg) : -1;
-        const bool third = greg >= 0 && greg != r0 && greg != r1;
-        unsigned long long km = contributed;
-        while (km) {
-          const int k = __ffsll((long long)km) - 1;
-          km &= km - 1;
-          const float e = E[k * kEStride + lane];
-          const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
-          unsigned long long rm = __ballot(third && e > 0.0f);
-          while (rm) {
-            const int l0 = __ffsll((long long)rm) - 1;
-            const int rr = __builtin_amdgcn_readlane(reg, l0);
-            const unsigned long long same = __ballot(reg == rr) & rm;
-            const float sum = wave_sum(((same >> lane) & 1ull) ? e : 0.0f);
-            if (lv.dense_F) {      // dense feature uplift: w F_r and w
+        unsigned long long rest = __ballot(greg >= 0 && greg != r0 && greg != r1);
+        while (rest) {               // one further region at a time: its pixels' weights per batch Gaussian
+          const int rr = __builtin_amdgcn_readlane(reg, __ffsll((long long)rest) - 1);
+          const unsigned long long same = __ballot(reg == rr) & rest;
+          rest &= ~same;
+          // lane gk of each lane group sums Gaussian gk's weights over the region's pixels in the group
+          float wr = 0.0f;
+          if (had) {
+            const unsigned long long mr = same >> gq0;
+#pragma unroll 8
+            for (int q = 0; q < B; ++q)
+              if ((mr >> q) & 1ull) wr += row[q];
+          }
+#pragma unroll
+          for (int o = B; o < 64; o <<= 1) wr += __shfl_xor(wr, o, 64);
+          // the region's code, loaded once (lane c holds slot c; longer codes are read per Gaussian)
+          const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
+          const bool held = !lv.dense_F && lv.k_code <= 64;
+          int cj = -1;
+          float cc = 0.0f;
+          if (held && lane < lv.k_code) {
+            cj = lv.code_idx[gr + lane];
+            cc = lv.code_val[gr + lane];
+            if (cj >= m_atoms) { atomicOr(&st->data_error, 2u); cj = -1; }
+          }
+          unsigned long long km = contributed;
+          while (km) {               // Gaussians with weight in the region: code (or feature) atomics
+            const int k = __ffsll((long long)km) - 1;
+            km &= km - 1;
+            const float sum = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wr), k));
+            if (!(sum > 0.0f)) continue;
+            const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
+            if (lv.dense_F) {        // dense feature uplift: w F_r and w
               const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
               const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
               for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
               if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
             } else {
               const unsigned long long arow = (unsigned long long)idk * (unsigned long long)m_atoms;
-              const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
-              for (int c = lane; c < lv.k_code; c += 64) {
-                const int jj = lv.code_idx[gr + c];
-                if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+              if (held) {
+                if (cj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)cj], sum * cc);
+              } else {
+                for (int c = lane; c < lv.k_code; c += 64) {
+                  const int jj = lv.code_idx[gr + c];
+                  if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+                  else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+                }
               }
             }
-            rm &= ~same;
           }
         }
       }
     }
+    key_cur = key_next;
+    key_next = key_after;
+    sp_cur = sp_next;
     __syncthreads();
   }
   unsigned long long total = count;
