@@ -69,15 +69,18 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   // pixel with one, r1 = first other region; pixels of further regions are
   // flagged (has2) and handled after each batch
   unsigned int has2 = 0u;                      // bit l: level l has pixels of a third region
+  int regs[kMaxLevels];                        // the pixel's region per level (-1: none or invalid)
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l) {
-    if (l >= n_levels) break;
+    regs[l] = -1;
+    if (l >= n_levels) continue;
     const LevelView& lv = args.lv[l];
     int reg = -1;
     if (inside) {
       reg = lv.rmap[(long long)py * W + px];
       if (reg < -1 || reg >= lv.n_regions) { atomicOr(&st->data_error, 1u); reg = -1; }
     }
+    regs[l] = reg;
     const unsigned long long any = __ballot(reg >= 0);
     const int r0 = any ? __builtin_amdgcn_readlane(reg, __ffsll((long long)any) - 1) : -1;
     const unsigned long long oth = __ballot(reg >= 0 && reg != r0);
@@ -101,17 +104,17 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   const int gq0 = lane - gk;                   // first pixel of the lane's group
   // the batch's ids and splats arrive ahead of use: the ids two batches
   // ahead and the splats one batch ahead are loaded while a batch composites
-  unsigned long long key_cur = gk < L ? keys[start + gk] : 0ull;
-  unsigned long long key_next = B + gk < L ? keys[start + B + gk] : 0ull;
-  GSplat sp_cur;
-  if (gk < L) sp_cur = splats[(unsigned int)key_cur];
+  // (indices past the list are clamped to its last entry: the loads stay
+  // unconditional, so nothing waits for them before their batch)
+  unsigned long long key_cur = keys[start + min(gk, L - 1)];
+  unsigned long long key_next = keys[start + min(B + gk, L - 1)];
+  GSplat sp_cur = splats[(unsigned int)key_cur];
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(T > 0.0f) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
-    GSplat sp_next;
-    if (j + B < L) sp_next = splats[(unsigned int)key_next];
-    const unsigned long long key_after = j + 2 * B < L ? keys[start + j + 2 * B] : 0ull;
+    const GSplat sp_next = splats[(unsigned int)key_next];
+    const unsigned long long key_after = keys[start + min(j + 2 * B, L - 1)];
     unsigned int my_id = 0;
     int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
     if (j < L) {                               // every lane group holds the batch's ids and boxes
@@ -198,9 +201,9 @@ __global__ __launch_bounds__(64) void k_composite_blk(
       for (int l = 0; l < kMaxLevels; ++l) {
         if (l >= n_levels || !((has2 >> l) & 1u)) continue;
         const LevelView& lv = args.lv[l];
-        const int reg = inside ? lv.rmap[(long long)py * W + px] : -1;
+        const int reg = regs[l];
         const int r0 = __float_as_int(s_rg[l][0]), r1 = __float_as_int(s_rg[l][1]);
-        const int greg = reg >= 0 && reg < lv.n_regions ? (int)(lv.region_base + reg) : -1;
+        const int greg = reg >= 0 ? (int)(lv.region_base + reg) : -1;
         unsigned long long rest = __ballot(greg >= 0 && greg != r0 && greg != r1);
         while (rest) {               // one further region at a time: its pixels' weights per batch Gaussian
           const int rr = __builtin_amdgcn_readlane(reg, __ffsll((long long)rest) - 1);
