@@ -40,7 +40,8 @@ int tiles_of(int w, int h, int shift = 4) {
 // Workspace layout of one binning pass (+ the uplift's per-view offsets and records).
 struct BinLayout {
   size_t status, splats, offsets, scan_part, tile_start, big_tiles, tile_order, bin_hist, radix_hist, tile_ids[2],
-      keys[2], records, total;
+      keys[2], records, extra, total;
+  unsigned int extra_cap;
   bool counting;
 };
 
@@ -66,6 +67,9 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
   L.keys[0] = off; off = align256(off + 8 * (size_t)cap);
   L.keys[1] = off; off = align256(off + 8 * (size_t)cap);
   L.records = off; off = align256(off + 16 * (size_t)cap * (size_t)rec_views);
+  // uplift: deferred weights of regions beyond a block's two record regions (one view at a time)
+  L.extra_cap = rec_views > 0 ? (unsigned int)std::max<int64_t>(1 << 18, std::min<int64_t>(cap / 16, 1 << 26)) : 0u;
+  L.extra = off; off = align256(off + 16 * (size_t)L.extra_cap);
   L.total = off;
   return L;
 }
@@ -310,6 +314,8 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   fill_bin(b, g, base, L, pair_capacity, 3, kSortCap);
   a.n_levels = n_levels;
   a.m_atoms = v->m_atoms;
+  a.extra = reinterpret_cast<float4*>(base + L.extra);
+  a.extra_cap = L.extra_cap;
   unsigned int* off_all = b.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
   const size_t rec_view = 2 * (size_t)pair_capacity;           // float2 per view and level
@@ -456,6 +462,8 @@ scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, 
   fill_bin(b, g, base, L, pair_capacity, 3, kSortCap);
   a.n_levels = 1;
   a.m_atoms = v->m_atoms;
+  a.extra = reinterpret_cast<float4*>(base + L.extra);
+  a.extra_cap = L.extra_cap;
   unsigned int* off_all = b.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
   LevelView& lv = a.lv[0];

@@ -64,7 +64,7 @@ struct LevelView {
   const int* code_idx;
   const float* code_val;
   int k_code;
-  float* acc;              // regions beyond a block's two record slots go here directly
+  float* acc;              // regions beyond a block's two record slots are added here (k_apply_extra)
   float2* records;         // [2 * capacity] (global region id as int bits, weight)
   const float* dense_F;    // dense feature uplift: region features [R x dense_d] (else NULL);
   int dense_d;             //   extra regions then add w F_r to acc (N x dense_d) and w to zsum
@@ -74,6 +74,8 @@ struct UpliftViewArgs {
   BinArgs bin;
   int n_levels, m_atoms;
   LevelView lv[kMaxLevels];
+  float4* extra;           // [extra_cap] deferred weights of regions beyond a block's two record
+  unsigned int extra_cap;  //   regions: (Gaussian id, level, global region id as int bits, weight)
 };
 hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s);
 

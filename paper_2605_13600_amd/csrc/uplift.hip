@@ -196,7 +196,7 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         rec[2ull * p + 1] = make_float2(s_rg[l][1], w1);
       }
     }
-    if (has2 && contributed) {   // third and further regions of the block: straight to the accumulator
+    if (has2 && contributed) {   // third and further regions of the block: deferred entries
 #pragma unroll
       for (int l = 0; l < kMaxLevels; ++l) {
         if (l >= n_levels || !((has2 >> l) & 1u)) continue;
@@ -219,37 +219,31 @@ __global__ __launch_bounds__(64) void k_composite_blk(
           }
 #pragma unroll
           for (int o = B; o < 64; o <<= 1) wr += __shfl_xor(wr, o, 64);
-          // the region's code, loaded once (lane c holds slot c; longer codes are read per Gaussian)
-          const long long gr = (lv.region_base + rr) * (long long)lv.k_code;
-          const bool held = !lv.dense_F && lv.k_code <= 64;
-          int cj = -1;
-          float cc = 0.0f;
-          if (held && lane < lv.k_code) {
-            cj = lv.code_idx[gr + lane];
-            cc = lv.code_val[gr + lane];
-            if (cj >= m_atoms) { atomicOr(&st->data_error, 2u); cj = -1; }
-          }
-          unsigned long long km = contributed;
-          while (km) {               // Gaussians with weight in the region: code (or feature) atomics
-            const int k = __ffsll((long long)km) - 1;
-            km &= km - 1;
-            const float sum = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wr), k));
-            if (!(sum > 0.0f)) continue;
-            const unsigned int idk = (unsigned int)__builtin_amdgcn_readlane((int)my_id, k);
-            if (lv.dense_F) {        // dense feature uplift: w F_r and w
-              const long long fr = (lv.region_base + rr) * (long long)lv.dense_d;
-              const unsigned long long drow = (unsigned long long)idk * (unsigned long long)lv.dense_d;
-              for (int c = lane; c < lv.dense_d; c += 64) atomic_add_f32(&lv.acc[drow + c], sum * lv.dense_F[fr + c]);
-              if (lane == 0) atomic_add_f32(&lv.zsum[idk], sum);
-            } else {
-              const unsigned long long arow = (unsigned long long)idk * (unsigned long long)m_atoms;
-              if (held) {
-                if (cj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)cj], sum * cc);
+          // deferred: one (Gaussian, level, region, weight) entry per batch Gaussian with weight in
+          // the region, applied to the accumulator by k_apply_extra after this view
+          const bool put = lane < nb && had && wr > 0.0f;
+          const unsigned long long pm = __ballot(put);
+          if (pm) {
+            unsigned int base = 0u;
+            if (lane == 0) base = atomicAdd(&st->n_extra, (unsigned int)__popcll(pm));
+            base = (unsigned int)__shfl((int)base, 0, 64);
+            if (put) {
+              const unsigned int slot = base + (unsigned int)__popcll(pm & ((1ull << lane) - 1ull));
+              const int greg = (int)(lv.region_base + rr);
+              if (slot < args.extra_cap) {
+                args.extra[slot] = make_float4(__uint_as_float(my_id), __int_as_float(l), __int_as_float(greg), wr);
+              } else if (lv.dense_F) {   // buffer full: add directly
+                const long long fr = (long long)greg * lv.dense_d;
+                const unsigned long long drow = (unsigned long long)my_id * (unsigned long long)lv.dense_d;
+                for (int c = 0; c < lv.dense_d; ++c) atomic_add_f32(&lv.acc[drow + c], wr * lv.dense_F[fr + c]);
+                atomic_add_f32(&lv.zsum[my_id], wr);
               } else {
-                for (int c = lane; c < lv.k_code; c += 64) {
+                const long long gr = (long long)greg * lv.k_code;
+                const unsigned long long arow = (unsigned long long)my_id * (unsigned long long)m_atoms;
+                for (int c = 0; c < lv.k_code; ++c) {
                   const int jj = lv.code_idx[gr + c];
                   if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                  else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], sum * lv.code_val[gr + c]);
+                  else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], wr * lv.code_val[gr + c]);
                 }
               }
             }
@@ -512,6 +506,36 @@ __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += s
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// The deferred further-region weights of one view: w times the region's code
+// (or feature, for the dense uplift) added to the Gaussian's accumulator row.
+__global__ __launch_bounds__(256) void k_apply_extra(UpliftViewArgs a, int m_atoms, Status* st) {
+  if (st->view_overflow) return;
+  const unsigned int n = min(st->n_extra, a.extra_cap);
+  for (unsigned int t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
+    const float4 r = a.extra[t];
+    const unsigned int id = __float_as_uint(r.x);
+    const int l = __float_as_int(r.y);
+    const long long greg = __float_as_int(r.z);
+    const float w = r.w;
+    if (l < 0 || l >= a.n_levels) continue;
+    const LevelView& lv = a.lv[l];
+    if (lv.dense_F) {
+      const long long fr = greg * lv.dense_d;
+      const unsigned long long drow = (unsigned long long)id * (unsigned long long)lv.dense_d;
+      for (int c = 0; c < lv.dense_d; ++c) atomic_add_f32(&lv.acc[drow + c], w * lv.dense_F[fr + c]);
+      atomic_add_f32(&lv.zsum[id], w);
+    } else {
+      const long long gr = greg * lv.k_code;
+      const unsigned long long arow = (unsigned long long)id * (unsigned long long)m_atoms;
+      for (int c = 0; c < lv.k_code; ++c) {
+        const int jj = lv.code_idx[gr + c];
+        if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+        else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], w * lv.code_val[gr + c]);
+      }
+    }
+  }
+}
+
 hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   hipError_t e = launch_bin_view(a.bin, s);
   if (e != hipSuccess) return e;
@@ -520,6 +544,9 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_composite_blk<kCompositeBatch>, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
+  if (a.extra_cap > 0)
+    hipLaunchKernelGGL(k_apply_extra, dim3(std::min(2048u, (a.extra_cap + 255) / 256)), dim3(256), 0, s, a,
+                       a.m_atoms, b.status);
   StageTimer::end(kStComposite, s);
   return hipGetLastError();
 }
