@@ -220,7 +220,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(unsigned long long* __restric
   }
   if (tid == 0 && st) {
     st->n_big = 0u;
-    st->n_extra = 0u;
+    st->n_extra = 0ull;
     const bool over = total > capacity;
     st->total_pairs = over ? 0u : (unsigned int)total;
     st->view_overflow = over ? 1u : 0u;

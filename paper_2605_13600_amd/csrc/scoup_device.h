@@ -108,8 +108,7 @@ struct Status {
   unsigned int max_pairs;       // largest per-view pair count seen
   unsigned int data_error;      // region id out of range
   unsigned int n_big;           // tiles of the current view sorted in global memory
-  unsigned int n_extra;         // deferred further-region weights of the current view
-  unsigned int pad;
+  unsigned long long n_extra;   // deferred further-region entry slots reserved in the current view
   unsigned long long contrib;   // contributions composited
 };
 

@@ -8,8 +8,8 @@
 //                    code (Sec. 4.1), so Algorithm 1's inner loop collapses to
 //                    one weight per (Gaussian, region) touch.  The first two
 //                    regions of a block go to fixed record slots of the
-//                    (Gaussian, block) pair; further regions are added to the
-//                    accumulator with atomics.
+//                    (Gaussian, block) pair; further regions become deferred
+//                    entries added to the accumulator after the view.
 //   k_rowbuild       Eq. 5 / Algorithm 1: w_i[j] += c_j * weight for every
 //                    record of Gaussian i over a batch of views, in LDS; rows
 //                    written once, coalesced; Eq. 6 Top-K fused on the last batch.
@@ -29,31 +29,60 @@ namespace scoup {
 // composite + per-(Gaussian, block, region) reduction: one 8x8 pixel block per
 // workgroup (one wave), lane l = pixel (l & 7, l >> 3) of the block, the
 // block's list already in depth order (binning).
-// Per batch of B depth-ordered Gaussians the wave writes every lane's weight
-// e into an LDS matrix E[Gaussian][pixel]; afterwards lane g B + k sums row k
-// over the pixels [g B, g B + B) of the block's two record regions (a
-// transposed reduction: no cross-lane traffic inside the sequential
-// compositing loop), the 64 / B partial sums are combined across lane groups
-// and the pair's two records are written.  Pixels of a third or further
-// region in the block (rare) are reduced across the wave and added to the
-// accumulator directly.  B trades LDS (B x 65 floats, which sets occupancy)
-// against the per-batch overhead.
+// Per batch of 32 depth-ordered Gaussians the wave writes every pixel's
+// weight e into an LDS matrix E[Gaussian][pixel] (no cross-lane traffic
+// inside the sequential compositing loop).  The batch's weight per
+// (Gaussian, region) is then the product of E with the block's 0/1 pixel-
+// membership matrix M[pixel][column], a dense contraction over the 64 pixels
+// done on the matrix cores (MFMA 16x16x4 f32: two tiles of 16 Gaussians by
+// 16 columns).  Columns 2l and 2l + 1 are level l's two record regions of
+// the block (the (Gaussian, block) pair's record slots); the columns after
+// them are further regions of the block, whose weights become deferred
+// entries that k_apply_extra adds to the accumulator after the view.
+// Regions beyond the 16 columns (blocks cut into many regions) are reduced
+// with a per-region loop over E.
 // ---------------------------------------------------------------------------
-constexpr int kEStride = 65;
-constexpr int kCompositeBatch = 32;
+constexpr int kEStride = 68;                 // 64 pixels + 4: rows 16-byte aligned, b128 reads conflict-free
+constexpr int kCompositeBatch = 32;          // two 16-row MFMA tiles
+constexpr int kCols = 16;                    // membership columns (one MFMA tile)
 
-template <int B>
-__global__ __launch_bounds__(64) void k_composite_blk(
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Adds w times region greg's code (or feature, for the dense uplift) to
+// Gaussian id's accumulator row of level view lv.
+__device__ __forceinline__ void add_region_direct(const int* code_idx, const float* code_val, int k_code,
+                                                  const float* dense_F, int dense_d, float* acc, float* zsum,
+                                                  unsigned int id, long long greg, float w, int m_atoms,
+                                                  Status* st) {
+  if (dense_F) {
+    const long long fr = greg * dense_d;
+    const unsigned long long drow = (unsigned long long)id * (unsigned long long)dense_d;
+    for (int c = 0; c < dense_d; ++c) atomic_add_f32(&acc[drow + c], w * dense_F[fr + c]);
+    atomic_add_f32(&zsum[id], w);
+  } else {
+    const long long gr = greg * k_code;
+    const unsigned long long arow = (unsigned long long)id * (unsigned long long)m_atoms;
+    for (int c = 0; c < k_code; ++c) {
+      const int jj = code_idx[gr + c];
+      if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+      else if (jj >= 0) atomic_add_f32(&acc[arow + (unsigned long long)jj], w * code_val[gr + c]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
-  static_assert(B == 16 || B == 32 || B == 64, "batch of 16, 32 or 64 Gaussians");
-  __shared__ float E[B * kEStride];
-  __shared__ float4 s_bs[3 * (B + 2)];        // the batch's splats, block-relative (three float4 each),
-                                              // two spare slots for the reads one step ahead
-  __shared__ unsigned long long s_mask[kMaxLevels][2];   // pixels of the block's two record regions
-  __shared__ float s_rg[kMaxLevels][2];                   // their global region ids (int bits; -1: none)
+  constexpr int B = kCompositeBatch;
+  __shared__ __align__(16) float E[B * kEStride];
+  __shared__ float4 s_bs[2 * (B + 2)];         // the batch's splats, block-relative: (hx, hy, fx, fy),
+  __shared__ float s_q[B + 2];                 //   (l00, l10, l11, opacity) and qmax; two spare slots
+                                               //   for the reads one step ahead
+  __shared__ __align__(16) unsigned int s_pidx[B];   // the batch Gaussians' pair (record) indices
+  __shared__ __align__(16) unsigned int s_gid[B];    // and ids
+  __shared__ unsigned long long s_excl[kMaxLevels];  // per level: pixels whose region has a column
   if (st->view_overflow) return;
   const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -64,15 +93,23 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   const int tile_x0 = tx * 8, tile_y0 = ty * 8;
   const int px = tile_x0 + lx, py = tile_y0 + ly;
   const bool inside = px < W && py < H;
-  // per level: the pixel's region (validated on every pixel, empty blocks
-  // included) and the block's two record regions r0 = region of the first
-  // pixel with one, r1 = first other region; pixels of further regions are
-  // flagged (has2) and handled after each batch
-  unsigned int has2 = 0u;                      // bit l: level l has pixels of a third region
+  // Per level: the pixel's region (validated on every pixel, empty blocks
+  // included); record regions r0 = region of the first pixel with one, r1 =
+  // first other region; then one column per further region while columns
+  // last.  Column masks and (level, global region) go through LDS (E's space,
+  // unused before the first batch).
+  unsigned long long* s_cm = reinterpret_cast<unsigned long long*>(E);   // [kCols] pixel masks
+  int* s_ci = reinterpret_cast<int*>(E + 2 * kCols);                    // [kCols][2] level, region
   int regs[kMaxLevels];                        // the pixel's region per level (-1: none or invalid)
+  int ncols = 2 * n_levels;
+  unsigned int spill = 0u;                     // bit l: level l has regions without a column
+  int rg0[kMaxLevels], rg1[kMaxLevels];        // per level: global ids of the two record regions (-1: none)
+  int pkey = 0;                                // bits 2l, 2l+1: the pixel's record slot at level l (2: none)
+  bool pvalid = false;                         // the pixel is in some record region
 #pragma unroll
   for (int l = 0; l < kMaxLevels; ++l) {
     regs[l] = -1;
+    rg0[l] = -1; rg1[l] = -1;
     if (l >= n_levels) continue;
     const LevelView& lv = args.lv[l];
     int reg = -1;
@@ -87,21 +124,75 @@ __global__ __launch_bounds__(64) void k_composite_blk(
     const int r1 = oth ? __builtin_amdgcn_readlane(reg, __ffsll((long long)oth) - 1) : -1;
     const unsigned long long m0 = __ballot(reg >= 0 && reg == r0);
     const unsigned long long m1 = __ballot(reg >= 0 && reg == r1);
-    if (__ballot(reg >= 0 && reg != r0 && reg != r1)) has2 |= 1u << l;
+    rg0[l] = r0 >= 0 ? (int)(lv.region_base + r0) : -1;
+    rg1[l] = r1 >= 0 ? (int)(lv.region_base + r1) : -1;
     if (lane == 0) {
-      s_mask[l][0] = m0; s_mask[l][1] = m1;
-      s_rg[l][0] = __int_as_float(r0 >= 0 ? (int)(lv.region_base + r0) : -1);
-      s_rg[l][1] = __int_as_float(r1 >= 0 ? (int)(lv.region_base + r1) : -1);
+      s_cm[2 * l] = m0; s_cm[2 * l + 1] = m1;
+      s_ci[4 * l] = l; s_ci[4 * l + 1] = rg0[l];
+      s_ci[4 * l + 2] = l; s_ci[4 * l + 3] = rg1[l];
     }
+    const int code = (reg >= 0 && reg == r0) ? 0 : ((reg >= 0 && reg == r1) ? 1 : 2);
+    pkey |= code << (2 * l);
+    pvalid = pvalid || code < 2;
+    unsigned long long covered = m0 | m1;
+    unsigned long long rest = __ballot(reg >= 0) & ~covered;
+    while (rest && ncols < kCols) {
+      const int rr = __builtin_amdgcn_readlane(reg, __ffsll((long long)rest) - 1);
+      const unsigned long long m = __ballot(reg == rr);
+      rest &= ~m;
+      covered |= m;
+      if (lane == 0) { s_cm[ncols] = m; s_ci[2 * ncols] = l; s_ci[2 * ncols + 1] = (int)(lv.region_base + rr); }
+      ++ncols;
+    }
+    if (rest) spill |= 1u << l;
+    if (lane == 0) s_excl[l] = covered;
   }
+  for (int l = n_levels; l < kMaxLevels; ++l) pkey |= 2 << (2 * l);
   if (L == 0) return;
+  // Pixel classes (same record slot at every level).  With no further
+  // regions and at most two classes, the reduction is two masked row sums
+  // of E per Gaussian (the common case); otherwise the MFMA product.
+  const unsigned long long vmask = __ballot(pvalid);
+  const int key0 = vmask ? __builtin_amdgcn_readlane(pkey, __ffsll((long long)vmask) - 1) : 0;
+  const unsigned long long cm0 = __ballot(pvalid && pkey == key0);
+  const unsigned long long rest1 = vmask & ~cm0;
+  const int key1 = rest1 ? __builtin_amdgcn_readlane(pkey, __ffsll((long long)rest1) - 1) : 0;
+  const unsigned long long cm1 = __ballot(pvalid && pkey == key1) & rest1;
+  const bool two_class = ncols == 2 * n_levels && (vmask & ~cm0 & ~cm1) == 0ull;
+  const bool full0 = cm0 == ~0ull;             // one class covering the whole block
+  // deferred entries of the further-region columns: one slot per (list
+  // entry, column), reserved at once (weights of zero included)
+  const int n_ext = ncols - 2 * n_levels;
+  unsigned long long ebase = 0ull;
+  if (n_ext > 0) {
+    if (lane == 0) ebase = atomicAdd(&st->n_extra, (unsigned long long)L * (unsigned long long)n_ext);
+    ebase = __shfl(ebase, 0, 64);
+  }
   __syncthreads();
+  // This lane's part of M and of the output: column col, K slot kk (pixels
+  // 16 kk .. 16 kk + 15, one per MFMA step), output rows 4 kk .. 4 kk + 3 of
+  // each 16-Gaussian tile.
+  const int col = lane & 15, kk = lane >> 4;
+  const bool rec_col = col < 2 * n_levels;
+  const bool ext_col = !rec_col && col < ncols;
+  unsigned int mbits = 0u;                     // bit s: M[16 kk + s][col]
+  int col_level = -1, col_greg = -1;
+  if (col < ncols) {
+    mbits = (unsigned int)(s_cm[col] >> (16 * kk)) & 0xFFFFu;
+    col_level = s_ci[2 * col];
+    col_greg = s_ci[2 * col + 1];
+  }
+  float2* rec_out = nullptr;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l)
+    if (rec_col && (col >> 1) == l) rec_out = args.lv[l].records;
+  __syncthreads();                             // column data read before E is overwritten
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
   float T = inside ? 1.0f : -1.0f;             // transmittance; negative once the pixel is finished
-  unsigned int count = 0u;                     // this pixel's contributions
-  const int gk = lane % B;                     // reduction: lane = group * B + Gaussian gk
-  const int gq0 = lane - gk;                   // first pixel of the lane's group
+  unsigned long long count = 0u;               // the block's contributions
+  const int gk = lane % B;                     // lane group g holds Gaussian gk of the batch
+  const int gq0 = lane - gk;                   // first pixel of the lane's group (per-region loop)
   // the batch's ids and splats arrive ahead of use: the ids two batches
   // ahead and the splats one batch ahead are loaded while a batch composites
   // (indices past the list are clamped to its last entry: the loads stay
@@ -109,28 +200,31 @@ __global__ __launch_bounds__(64) void k_composite_blk(
   unsigned long long key_cur = keys[start + min(gk, L - 1)];
   unsigned long long key_next = keys[start + min(B + gk, L - 1)];
   GSplat sp_cur = splats[(unsigned int)key_cur];
+  unsigned int off_cur = off[(unsigned int)key_cur];   // the Gaussian's first pair (record) index
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(T > 0.0f) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
     const GSplat sp_next = splats[(unsigned int)key_next];
+    const unsigned int off_next = off[(unsigned int)key_next];
     const unsigned long long key_after = keys[start + min(j + 2 * B, L - 1)];
     unsigned int my_id = 0;
-    int own_bx0 = 0, own_bx1 = 0, own_by0 = 0;
-    if (j < L) {                               // every lane group holds the batch's ids and boxes
+    if (j < L) {
       my_id = (unsigned int)key_cur;
-      const GSplat gg = sp_cur;
-      own_bx0 = gg.bx0; own_bx1 = gg.bx1; own_by0 = gg.by0;
       if (lane < B) {                          // LDS copy read back as a broadcast in the loop
+        const GSplat gg = sp_cur;
         BlockSplat bs;
         bs.load(gg, tile_x0, tile_y0);
-        s_bs[3 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
-        s_bs[3 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
-        s_bs[3 * lane + 2] = make_float4(bs.qmax, 0.0f, 0.0f, 0.0f);
+        s_bs[2 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
+        s_bs[2 * lane + 1] = make_float4(bs.l00, bs.l10, bs.l11, bs.opacity);
+        s_q[lane] = bs.qmax;
+        const int bx0 = gg.bx0 >> 3, bx1 = gg.bx1 >> 3, by0 = gg.by0 >> 3;
+        s_pidx[lane] = off_cur + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
+        s_gid[lane] = my_id;
       }
     }
     __syncthreads();
-    unsigned int contrib = 0u;                 // bit k: this pixel got e > 0 from batch Gaussian k
+    unsigned int contrib = 0u;                 // bit k: batch Gaussian k gave some pixel e > 0
     if (!all_done) {
       // one Gaussian of the batch, without branches: T < 0 marks a finished pixel
       auto step = [&](int k, const float4& c0, const float4& c1, float cq) {
@@ -144,68 +238,155 @@ __global__ __launch_bounds__(64) void k_composite_blk(
         const bool keep = take && testT >= kTMin;
         E[k * kEStride + lane] = keep ? alpha * T : 0.0f;
         T = take ? (keep ? testT : -1.0f) : T;
-        contrib |= (keep ? 1u : 0u) << k;
-        count += keep ? 1u : 0u;
+        const unsigned long long kb = __ballot(keep);   // scalar bookkeeping
+        contrib |= (kb ? 1u : 0u) << k;
+        count += (unsigned long long)__popcll(kb);
       };
       // two register sets alternate so that each Gaussian's splat is read
       // from LDS one step ahead without copies
       float4 a0 = s_bs[0], a1 = s_bs[1];
-      float aq = s_bs[2].x;
+      float aq = s_q[0];
       for (int k = 0; k < nb; k += 2) {
         // slots past the batch hold stale data; they are never used
-        const float4 b0 = s_bs[3 * k + 3], b1 = s_bs[3 * k + 4];
-        const float bq = s_bs[3 * k + 5].x;
+        const float4 b0v = s_bs[2 * k + 2], b1v = s_bs[2 * k + 3];
+        const float bq = s_q[k + 1];
         step(k, a0, a1, aq);
         if (k + 1 >= nb) break;
-        a0 = s_bs[3 * k + 6]; a1 = s_bs[3 * k + 7]; aq = s_bs[3 * k + 8].x;
-        step(k + 1, b0, b1, bq);
+        a0 = s_bs[2 * k + 4]; a1 = s_bs[2 * k + 5]; aq = s_q[k + 2];
+        step(k + 1, b0v, b1v, bq);
         if (__ballot(T > 0.0f) == 0ull) break;
       }
     }
-    unsigned int cw = contrib;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) cw |= (unsigned int)__shfl_xor((int)cw, o, 64);
-    const unsigned long long contributed = cw;
+    const unsigned long long contributed = contrib;
     __syncthreads();
-    // every pair's two record slots per level are written, zero weight included
-    const bool had = gk < nb && ((contributed >> gk) & 1ull);
-    const float* row = E + gk * kEStride + gq0;
-    const int bx0 = own_bx0 >> 3, bx1 = own_bx1 >> 3, by0 = own_by0 >> 3;
+    if (two_class) {
+      // lane group g sums Gaussian gk's row over the group's pixels of each
+      // class; rows of Gaussians without a contribution (stale ones included)
+      // are not read
+      float S0 = 0.0f, S1 = 0.0f;
+      if (gk < nb && ((contributed >> gk) & 1ull)) {
+        const float4* row4 = reinterpret_cast<const float4*>(E + gk * kEStride + gq0);
+        if (full0) {
 #pragma unroll
-    for (int l = 0; l < kMaxLevels; ++l) {
-      if (l >= n_levels) break;
-      float w0 = 0.0f, w1 = 0.0f;
-      if (had) {
-        const unsigned long long m0 = s_mask[l][0] >> gq0, m1 = s_mask[l][1] >> gq0;
-#pragma unroll 8
-        for (int q = 0; q < B; ++q) {
-          const float x = row[q];
-          if ((m0 >> q) & 1ull) w0 += x;
-          else if ((m1 >> q) & 1ull) w1 += x;
+          for (int q = 0; q < B / 4; ++q) {
+            const float4 x = row4[q];
+            S0 += (x.x + x.y) + (x.z + x.w);
+          }
+        } else {
+          const unsigned int b0 = (unsigned int)(cm0 >> gq0), b1 = (unsigned int)(cm1 >> gq0);
+#pragma unroll
+          for (int q = 0; q < B / 4; ++q) {
+            const float4 x = row4[q];
+            const float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              S0 += ((b0 >> (4 * q + m)) & 1u) ? xs[m] : 0.0f;
+              S1 += ((b1 >> (4 * q + m)) & 1u) ? xs[m] : 0.0f;
+            }
+          }
         }
       }
 #pragma unroll
       for (int o = B; o < 64; o <<= 1) {       // combine the lane groups
-        w0 += __shfl_xor(w0, o, 64);
-        w1 += __shfl_xor(w1, o, 64);
+        S0 += __shfl_xor(S0, o, 64);
+        S1 += __shfl_xor(S1, o, 64);
       }
-      if (lane < nb) {
-        const unsigned int p = off[my_id] + (unsigned int)((ty - by0) * (bx1 - bx0 + 1) + (tx - bx0));
-        float2* rec = args.lv[l].records;
-        rec[2ull * p] = make_float2(s_rg[l][0], w0);
-        rec[2ull * p + 1] = make_float2(s_rg[l][1], w1);
+      if (lane < nb) {                         // every pair's record slots, zero weight included
+        const unsigned int p = s_pidx[lane];
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+          if (l >= n_levels) break;
+          const int c0 = (key0 >> (2 * l)) & 3, c1 = (key1 >> (2 * l)) & 3;
+          const float w0 = (c0 == 0 ? S0 : 0.0f) + (c1 == 0 ? S1 : 0.0f);
+          const float w1 = (c0 == 1 ? S0 : 0.0f) + (c1 == 1 ? S1 : 0.0f);
+          float2* rec = args.lv[l].records;
+          rec[2ull * p] = make_float2(__int_as_float(rg0[l]), w0);
+          rec[2ull * p + 1] = make_float2(__int_as_float(rg1[l]), w1);
+        }
+      }
+    } else {
+    // W = E M on the matrix cores; rows of Gaussians that did not contribute
+    // (stale E rows included) are replaced by zero below
+    f4v acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (contributed) {
+      const float* e0 = E + (lane & 15) * kEStride + 16 * kk;
+      const float* e1 = e0 + 16 * kEStride;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 x0 = *reinterpret_cast<const float4*>(e0 + 4 * q);
+        const float4 x1 = *reinterpret_cast<const float4*>(e1 + 4 * q);
+        const float xa[4] = {x0.x, x0.y, x0.z, x0.w}, xb[4] = {x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const float bv = (float)((mbits >> (4 * q + m)) & 1u);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[m], bv, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xb[m], bv, acc1, 0, 0, 0);
+        }
       }
     }
-    if (has2 && contributed) {   // third and further regions of the block: deferred entries
+    // lane holds W[g][col] for g = 4 kk + r (acc0) and 16 + 4 kk + r (acc1);
+    // rows of Gaussians without a contribution count as zero
+    auto wval = [&](int i) {
+      const int g = (i < 4 ? 0 : 16) + 4 * kk + (i & 3);
+      const float a = i < 4 ? acc0[i & 3] : acc1[i & 3];
+      return ((contributed >> g) & 1ull) ? a : 0.0f;
+    };
+    if (rec_col) {                             // every pair's record slots, zero weight included
+      const float rg = __int_as_float(col_greg);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const uint4 p4 = *reinterpret_cast<const uint4*>(&s_pidx[16 * t + 4 * kk]);
+        const unsigned int pp[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (16 * t + 4 * kk + r < nb) rec_out[2ull * pp[r] + (col & 1)] = make_float2(rg, wval(4 * t + r));
+      }
+    }
+    if (n_ext > 0) {                           // further-region columns: this batch's entry slots
+      unsigned int ovf = 0u;
+      if (ext_col) {
+        const unsigned long long row0 = ebase + (unsigned long long)b0 * n_ext + (unsigned long long)(col - 2 * n_levels);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int g = (i < 4 ? 0 : 16) + 4 * kk + (i & 3);
+          if (g < nb) {
+            const unsigned long long slot = row0 + (unsigned long long)g * n_ext;
+            const float w = wval(i);
+            if (slot < args.extra_cap)
+              args.extra[slot] = make_float4(__uint_as_float(s_gid[g]), __int_as_float(col_level),
+                                             __int_as_float(col_greg), w);
+            else if (w > 0.0f)
+              ovf |= 1u << i;
+          }
+        }
+      }
+      if (__ballot(ovf != 0u)) {               // entry buffer full: add directly
+        const int* ci = nullptr; const float* cv = nullptr; const float* dF = nullptr;
+        float* ac = nullptr; float* zs = nullptr; int kc = 0, dd = 0;
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l)
+          if (l == col_level) {
+            ci = args.lv[l].code_idx; cv = args.lv[l].code_val; kc = args.lv[l].k_code;
+            dF = args.lv[l].dense_F; dd = args.lv[l].dense_d; ac = args.lv[l].acc; zs = args.lv[l].zsum;
+          }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if ((ovf >> i) & 1u)
+            add_region_direct(ci, cv, kc, dF, dd, ac, zs, s_gid[(i < 4 ? 0 : 16) + 4 * kk + (i & 3)], col_greg,
+                              wval(i), m_atoms, st);
+      }
+    }
+    }
+    if (spill && contributed) {  // regions without a column (many regions in the block): one at a time
+      const bool had = gk < nb && ((contributed >> gk) & 1ull);
+      const float* row = E + gk * kEStride + gq0;
 #pragma unroll
       for (int l = 0; l < kMaxLevels; ++l) {
-        if (l >= n_levels || !((has2 >> l) & 1u)) continue;
+        if (l >= n_levels || !((spill >> l) & 1u)) continue;
         const LevelView& lv = args.lv[l];
         const int reg = regs[l];
-        const int r0 = __float_as_int(s_rg[l][0]), r1 = __float_as_int(s_rg[l][1]);
-        const int greg = reg >= 0 ? (int)(lv.region_base + reg) : -1;
-        unsigned long long rest = __ballot(greg >= 0 && greg != r0 && greg != r1);
-        while (rest) {               // one further region at a time: its pixels' weights per batch Gaussian
+        unsigned long long rest = __ballot(reg >= 0) & ~s_excl[l];
+        while (rest) {
           const int rr = __builtin_amdgcn_readlane(reg, __ffsll((long long)rest) - 1);
           const unsigned long long same = __ballot(reg == rr) & rest;
           rest &= ~same;
@@ -213,52 +394,24 @@ __global__ __launch_bounds__(64) void k_composite_blk(
           float wr = 0.0f;
           if (had) {
             const unsigned long long mr = same >> gq0;
-#pragma unroll 8
             for (int q = 0; q < B; ++q)
               if ((mr >> q) & 1ull) wr += row[q];
           }
 #pragma unroll
           for (int o = B; o < 64; o <<= 1) wr += __shfl_xor(wr, o, 64);
-          // deferred: one (Gaussian, level, region, weight) entry per batch Gaussian with weight in
-          // the region, applied to the accumulator by k_apply_extra after this view
-          const bool put = lane < nb && had && wr > 0.0f;
-          const unsigned long long pm = __ballot(put);
-          if (pm) {
-            unsigned int base = 0u;
-            if (lane == 0) base = atomicAdd(&st->n_extra, (unsigned int)__popcll(pm));
-            base = (unsigned int)__shfl((int)base, 0, 64);
-            if (put) {
-              const unsigned int slot = base + (unsigned int)__popcll(pm & ((1ull << lane) - 1ull));
-              const int greg = (int)(lv.region_base + rr);
-              if (slot < args.extra_cap) {
-                args.extra[slot] = make_float4(__uint_as_float(my_id), __int_as_float(l), __int_as_float(greg), wr);
-              } else if (lv.dense_F) {   // buffer full: add directly
-                const long long fr = (long long)greg * lv.dense_d;
-                const unsigned long long drow = (unsigned long long)my_id * (unsigned long long)lv.dense_d;
-                for (int c = 0; c < lv.dense_d; ++c) atomic_add_f32(&lv.acc[drow + c], wr * lv.dense_F[fr + c]);
-                atomic_add_f32(&lv.zsum[my_id], wr);
-              } else {
-                const long long gr = (long long)greg * lv.k_code;
-                const unsigned long long arow = (unsigned long long)my_id * (unsigned long long)m_atoms;
-                for (int c = 0; c < lv.k_code; ++c) {
-                  const int jj = lv.code_idx[gr + c];
-                  if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-                  else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], wr * lv.code_val[gr + c]);
-                }
-              }
-            }
-          }
+          if (lane < nb && had && wr > 0.0f)
+            add_region_direct(lv.code_idx, lv.code_val, lv.k_code, lv.dense_F, lv.dense_d, lv.acc, lv.zsum, my_id,
+                              lv.region_base + rr, wr, m_atoms, st);
         }
       }
     }
     key_cur = key_next;
     key_next = key_after;
     sp_cur = sp_next;
+    off_cur = off_next;
     __syncthreads();
   }
-  unsigned long long total = count;
-  for (int o = 32; o >= 1; o >>= 1) total += __shfl_xor(total, o, 64);
-  if (lane == 0 && total) atomicAdd(&st->contrib, total);
+  if (lane == 0 && count) atomicAdd(&st->contrib, count);
 }
 
 // Eq. 6 on one row held by a wave (values in LDS or global memory).
@@ -510,29 +663,18 @@ __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += s
 // (or feature, for the dense uplift) added to the Gaussian's accumulator row.
 __global__ __launch_bounds__(256) void k_apply_extra(UpliftViewArgs a, int m_atoms, Status* st) {
   if (st->view_overflow) return;
-  const unsigned int n = min(st->n_extra, a.extra_cap);
-  for (unsigned int t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
+  const unsigned long long n = min(st->n_extra, (unsigned long long)a.extra_cap);
+  for (unsigned long long t = blockIdx.x * 256ull + threadIdx.x; t < n; t += gridDim.x * 256ull) {
     const float4 r = a.extra[t];
-    const unsigned int id = __float_as_uint(r.x);
+    if (!(r.w > 0.0f)) continue;             // reserved slot of a Gaussian without weight there
     const int l = __float_as_int(r.y);
-    const long long greg = __float_as_int(r.z);
-    const float w = r.w;
-    if (l < 0 || l >= a.n_levels) continue;
-    const LevelView& lv = a.lv[l];
-    if (lv.dense_F) {
-      const long long fr = greg * lv.dense_d;
-      const unsigned long long drow = (unsigned long long)id * (unsigned long long)lv.dense_d;
-      for (int c = 0; c < lv.dense_d; ++c) atomic_add_f32(&lv.acc[drow + c], w * lv.dense_F[fr + c]);
-      atomic_add_f32(&lv.zsum[id], w);
-    } else {
-      const long long gr = greg * lv.k_code;
-      const unsigned long long arow = (unsigned long long)id * (unsigned long long)m_atoms;
-      for (int c = 0; c < lv.k_code; ++c) {
-        const int jj = lv.code_idx[gr + c];
-        if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
-        else if (jj >= 0) atomic_add_f32(&lv.acc[arow + (unsigned long long)jj], w * lv.code_val[gr + c]);
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k)
+      if (k == l && k < a.n_levels) {
+        const LevelView& lv = a.lv[k];
+        add_region_direct(lv.code_idx, lv.code_val, lv.k_code, lv.dense_F, lv.dense_d, lv.acc, lv.zsum,
+                          __float_as_uint(r.x), __float_as_int(r.z), r.w, m_atoms, st);
       }
-    }
   }
 }
 
@@ -541,7 +683,7 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_blk<kCompositeBatch>, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
+  hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
   if (a.extra_cap > 0)

@@ -230,3 +230,68 @@ def test_dense_feature_uplift_against_oracle(d):
     nrm = np.linalg.norm(f_ref, axis=1)
     err = np.linalg.norm(fg - f_ref, axis=1)
     assert (err[ok] <= 1e-5 * nrm[ok] + 1e-7).all(), float((err[ok] / np.maximum(nrm[ok], 1e-30)).max())
+
+
+def _regions_per_block(v):
+    """Largest number of distinct regions in one 8x8 block over the views."""
+    best = 0
+    for m in v.region_maps:
+        H, W = m.shape
+        for y in range(0, H, 8):
+            for x in range(0, W, 8):
+                r = m[y:y + 8, x:x + 8]
+                best = max(best, len(np.unique(r[r >= 0])))
+    return best
+
+
+@pytest.mark.parametrize("sites", [150, 1200])
+def test_fragmented_regions_per_block(sites):
+    """Voronoi maps fine enough that 8x8 blocks hold many regions: the block's
+    two record regions, the further-region columns (deferred entries) and,
+    at 1200 cells, regions beyond the 16 membership columns (per-region loop)."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    v = sg.make_views(910 + sites, sc.views.cameras, sites, 64, 4, hole_sites=3)
+    rb = _regions_per_block(v)
+    assert rb >= (17 if sites == 1200 else 4), rb
+    _compare(sc.gaussians, v, 4, f"fragmented{sites}")
+
+
+def test_fragmented_levels_in_one_pass():
+    """Four levels (coarse to very fine) in one compositing pass: 8 record
+    columns, the remaining 8 columns shared by the fine levels' further
+    regions, the rest through the per-region loop; every level matches the
+    oracle run on that level alone."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    levels = [sg.make_views(700 + s, sc.views.cameras, s, 64, 4, hole_sites=1) for s in (6, 60, 300, 1000)]
+    dg = P.gaussians_to_device(sc.gaussians)
+    idxs, vals, accs, nc = P.uplift_levels(dg, [P.views_to_device(v) for v in levels], 4)
+    torch.cuda.synchronize()
+    for lvl, v in enumerate(levels):
+        ref = OU.uplift_accumulate(sc.gaussians, v)
+        sa = PT.check_acc(accs[lvl].cpu().numpy(), ref.acc, ref.amb)
+        PT.check_topk(idxs[lvl].cpu().numpy(), vals[lvl].cpu().numpy(), ref.acc, ref.amb, 4)
+        assert abs(nc - ref.n_contrib) <= ref.count_slack
+        print(f"[fragmented level {lvl}] acc={sa}")
+
+
+def test_dense_feature_uplift_fragmented():
+    """Eq. 3 with many regions per block: further regions add w F_r and w
+    through the deferred entries and the per-region loop."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    v = sg.make_views(933, sc.views.cameras, 1200, 64, 4, hole_sites=3)
+    C = sg.random_codebook(32, 64, 64)
+    dg, dv = to_device(sc.gaussians, v)
+    feat, z, nc = P.uplift_dense(dg, dv, torch.from_numpy(C).cuda())
+    torch.cuda.synchronize()
+    f_ref, z_ref = OU.dense_uplift(sc.gaussians, v, C)
+    amb = OU.uplift_accumulate(sc.gaussians, v).amb
+    ok = amb.sum(1) == 0
+    zr = z.cpu().numpy().astype(np.float64)
+    assert np.allclose(zr[ok], z_ref[ok], rtol=1e-5, atol=1e-9)
+    fg = feat.cpu().numpy().astype(np.float64)
+    nrm = np.linalg.norm(f_ref, axis=1)
+    err = np.linalg.norm(fg - f_ref, axis=1)
+    assert (err[ok] <= 1e-5 * nrm[ok] + 1e-7).all(), float((err[ok] / np.maximum(nrm[ok], 1e-30)).max())
