@@ -258,10 +258,10 @@ __global__ __launch_bounds__(256) void k_scan_down(unsigned int* __restrict__ da
 // Gaussian-major pair emission
 // ---------------------------------------------------------------------------
 // Blocks the Gaussian cannot reach get the tile id n_tiles, which sorts after
-// every list and belongs to none, and zero uplift records.
+// every list and belongs to none.
 __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n, int tiles_x,
                                               int n_tiles, int tile_shift, int W, int H,
-                                              const unsigned int* __restrict__ off, CullRecords cull,
+                                              const unsigned int* __restrict__ off,
                                               unsigned int* __restrict__ tile_ids,
                                               unsigned long long* __restrict__ keys, const Status* st) {
   if (st->view_overflow) return;
@@ -280,12 +280,19 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
       const bool live = pair_live(s, bc, r, tx, ty);
       tile_ids[p] = live ? (unsigned int)(ty * tiles_x + tx) : (unsigned int)n_tiles;
       keys[p] = key;
-      if (!live)
-        for (int l = 0; l < cull.n; ++l) {
-          cull.rec[l][2ull * p] = make_float2(__int_as_float(-1), 0.0f);
-          cull.rec[l][2ull * p + 1] = make_float2(__int_as_float(-1), 0.0f);
-        }
     }
+}
+
+// Every pair's uplift record slots start as (no region, 0): coalesced over
+// the view's pairs; the compositing overwrites those of reachable blocks.
+__global__ __launch_bounds__(256) void k_clear_records(CullRecords cull, const Status* st) {
+  if (st->view_overflow) return;
+  const unsigned long long n = st->total_pairs;
+  const float4 z = make_float4(__int_as_float(-1), 0.0f, __int_as_float(-1), 0.0f);
+  for (int l = 0; l < cull.n; ++l) {
+    float4* r = reinterpret_cast<float4*>(cull.rec[l]);
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) r[i] = z;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -356,7 +363,6 @@ __global__ __launch_bounds__(256) void k_bin_colscan(unsigned int* __restrict__ 
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __restrict__ splats, long long n,
                                                              int tiles_x, int n_tiles, int tile_shift, int W, int H,
-                                                             const unsigned int* __restrict__ off, CullRecords cull,
                                                              long long per_wg, const unsigned int* __restrict__ hist,
                                                              const unsigned int* __restrict__ tile_start,
                                                              unsigned long long* __restrict__ keys,
@@ -375,18 +381,11 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
     const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
-    unsigned int p = off[i];                   // Gaussian-major pair index (uplift records)
     const BlockCull bc(g, tile_shift, W, H);
     int r = 0;
     for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx, ++p, ++r) {
-        if (!pair_live(g, bc, r, tx, ty)) {
-          for (int l = 0; l < cull.n; ++l) {
-            cull.rec[l][2ull * p] = make_float2(__int_as_float(-1), 0.0f);
-            cull.rec[l][2ull * p + 1] = make_float2(__int_as_float(-1), 0.0f);
-          }
-          continue;
-        }
+      for (int tx = tx0; tx <= tx1; ++tx, ++r) {
+        if (!pair_live(g, bc, r, tx, ty)) continue;
         const int t = ty * tiles_x + tx;
         const unsigned int sh = 16 * (t & 1);
         const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
@@ -715,11 +714,13 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   if (a.n > 0 && !counting) {
     StageTimer::begin(kStEmit, s);
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.n_tiles, a.tile_shift,
-                       a.cam.width, a.cam.height, (const unsigned int*)a.offsets, cull_of(a),
-                       a.tile_ids[0], a.keys[0], a.status);
+                       a.cam.width, a.cam.height, (const unsigned int*)a.offsets, a.tile_ids[0], a.keys[0],
+                       a.status);
     StageTimer::end(kStEmit, s);
   }
   StageTimer::begin(kStSortBig, s);
+  if (a.n_cull_records > 0 && a.n > 0)
+    hipLaunchKernelGGL(k_clear_records, dim3(1024), dim3(256), 0, s, cull_of(a), (const Status*)a.status);
   if (counting) {
     const int nwg = count_groups(a.n);
     const long long per_wg = std::max<long long>(1, (a.n + nwg - 1) / nwg);
@@ -734,8 +735,8 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_down, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part,
                        a.tile_start + a.n_tiles);
     hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
-                       a.tile_shift, a.cam.width, a.cam.height, (const unsigned int*)a.offsets, cull_of(a), per_wg,
-                       (const unsigned int*)a.bin_hist, (const unsigned int*)a.tile_start, a.keys[0], a.status);
+                       a.tile_shift, a.cam.width, a.cam.height, per_wg, (const unsigned int*)a.bin_hist,
+                       (const unsigned int*)a.tile_start, a.keys[0], a.status);
     hipLaunchKernelGGL(k_bin_big, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.tile_start, a.n_tiles,
                        a.sort_cap, a.big_tiles, a.status);
     a.sorted = 0;
