@@ -668,6 +668,208 @@ __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restr
   for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[bucket(t)], 1u)] = (unsigned int)t;
 }
 
+// ---------------------------------------------------------------------------
+// Depth order of a block list of at most 64 R keys by one wave: element
+// e = r 64 + lane sits in register r of lane `lane`.  The bitonic network is
+// the all-ascending form (per merge size k a mirror stage pairing e with
+// e ^ (k - 1), then half-cleaners pairing e with e ^ j, the smaller key
+// always to the lower index), so the ~0 padding past the list never moves
+// down: registers holding padding only are skipped, and the network stops
+// at the list's power-of-two size.  Distances of 64 and more pair registers
+// of one lane; shorter ones exchange across lanes (DPP, swizzle or
+// bpermute).  No LDS, no barriers.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  else if constexpr (M == 3) return __builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, false);   // quad_perm 3,2,1,0
+  else if constexpr (M == 7) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  else if constexpr (M == 15) return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); // row_mirror
+  else if constexpr (M < 32) return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F);          // xor within 32
+  else return __shfl_xor(v, M, 64);
+}
+
+template <int M>
+__device__ __forceinline__ unsigned long long lane_xor64(unsigned long long x) {
+  const unsigned int lo = (unsigned int)lane_xor<M>((int)(unsigned int)x);
+  const unsigned int hi = (unsigned int)lane_xor<M>((int)(unsigned int)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// one cross-lane stage with partner lane ^ M; the lower index keeps the
+// smaller key (`hb` = the partner's distinguishing lane bit)
+template <int R, int M, int HB>
+__device__ __forceinline__ void wave_cross_stage(unsigned long long (&v)[R], int rr, int lane) {
+  const bool lower = (lane & HB) == 0;
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    if (r < rr) {
+      const unsigned long long w = lane_xor64<M>(v[r]);
+      const bool take = lower ? (w < v[r]) : (w > v[r]);
+      v[r] = take ? w : v[r];
+    }
+  }
+}
+
+// half-cleaners j = jmax .. 1 for j < 64
+template <int R>
+__device__ __forceinline__ void wave_cross_cleaners(unsigned long long (&v)[R], int jmax, int rr, int lane) {
+  if (jmax >= 32) wave_cross_stage<R, 32, 32>(v, rr, lane);
+  if (jmax >= 16) wave_cross_stage<R, 16, 16>(v, rr, lane);
+  if (jmax >= 8) wave_cross_stage<R, 8, 8>(v, rr, lane);
+  if (jmax >= 4) wave_cross_stage<R, 4, 4>(v, rr, lane);
+  if (jmax >= 2) wave_cross_stage<R, 2, 2>(v, rr, lane);
+  if (jmax >= 1) wave_cross_stage<R, 1, 1>(v, rr, lane);
+}
+
+// register half-cleaner: registers r and r ^ S (S = j / 64)
+template <int R, int S>
+__device__ __forceinline__ void wave_reg_stage(unsigned long long (&v)[R], int rr) {
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    if ((r & S) || (r ^ S) >= rr) continue;
+    const unsigned long long a = v[r], b = v[r ^ S];
+    const bool sw = b < a;
+    v[r] = sw ? b : a;
+    v[r ^ S] = sw ? a : b;
+  }
+}
+
+// mirror stage for k >= 128 (S = k / 64 - 1): register r pairs with register
+// r ^ S of lane 63 - lane
+template <int R, int S>
+__device__ __forceinline__ void wave_mirror_stage(unsigned long long (&v)[R], int rr) {
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    if ((r ^ S) < r || (r ^ S) >= rr) continue;      // r is the lower register of the pair
+    const unsigned long long a = v[r], b = v[r ^ S];
+    const unsigned long long bm = lane_xor64<63>(b), am = lane_xor64<63>(a);
+    v[r] = bm < a ? bm : a;
+    v[r ^ S] = am > b ? am : b;
+  }
+}
+
+// the network up to merge size n2 (<= 64 R) on one wave's registers
+template <int R>
+__device__ __forceinline__ void wave_sort_regs(unsigned long long (&v)[R], int n2, int rr, int lane) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    if (k <= 64) {                             // mirror within k lanes
+      switch (k) {
+        case 2: wave_cross_stage<R, 1, 1>(v, rr, lane); break;
+        case 4: wave_cross_stage<R, 3, 2>(v, rr, lane); break;
+        case 8: wave_cross_stage<R, 7, 4>(v, rr, lane); break;
+        case 16: wave_cross_stage<R, 15, 8>(v, rr, lane); break;
+        case 32: wave_cross_stage<R, 31, 16>(v, rr, lane); break;
+        default: wave_cross_stage<R, 63, 32>(v, rr, lane); break;
+      }
+    } else {                                   // mirror across registers, then register half-cleaners
+      const int S = (k >> 6) - 1;
+      if constexpr (R >= 2) if (S == 1) wave_mirror_stage<R, 1>(v, rr);
+      if constexpr (R >= 4) if (S == 3) wave_mirror_stage<R, 3>(v, rr);
+      if constexpr (R >= 8) if (S == 7) wave_mirror_stage<R, 7>(v, rr);
+      const int jr = k >> 8;
+      if constexpr (R >= 8) if (jr >= 4) wave_reg_stage<R, 4>(v, rr);
+      if constexpr (R >= 4) if (jr >= 2) wave_reg_stage<R, 2>(v, rr);
+      if constexpr (R >= 2) if (jr >= 1) wave_reg_stage<R, 1>(v, rr);
+    }
+    wave_cross_cleaners<R>(v, k <= 64 ? (k >> 2) : 32, rr, lane);
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void wave_sort_list(unsigned long long* __restrict__ s, int L, int lane) {
+  unsigned long long v[R];
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    const int e = r * 64 + lane;
+    v[r] = e < L ? s[e] : ~0ull;
+  }
+  int n2 = 2;
+  while (n2 < L) n2 <<= 1;
+  wave_sort_regs<R>(v, n2, (L + 63) >> 6, lane);
+#pragma clang loop unroll(full)
+  for (int r = 0; r < R; ++r) {
+    const int e = r * 64 + lane;
+    if (e < L) s[e] = v[r];
+  }
+}
+
+constexpr int kWaveSortMax = 512;              // lists up to this length: one wave each
+constexpr int kWgSortMax = 2048;               // up to this length: 2 or 4 waves of 512
+
+// one wave per block list (longest first); lists of 2 .. kWaveSortMax keys
+__global__ __launch_bounds__(256) void k_sort_lists_wave(unsigned long long* __restrict__ keys,
+                                                         const unsigned int* __restrict__ tile_start,
+                                                         const unsigned int* __restrict__ order, int n_tiles,
+                                                         const Status* st) {
+  if (st->view_overflow) return;
+  const int w = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (w >= n_tiles) return;
+  const int lane = threadIdx.x & 63;
+  const int tile = order ? (int)order[w] : w;
+  const unsigned int start = tile_start[tile];
+  const int L = (int)(tile_start[tile + 1] - start);
+  if (L < 2 || L > kWaveSortMax) return;
+  unsigned long long* s = keys + start;
+  if (L <= 128) wave_sort_list<2>(s, L, lane);
+  else if (L <= 256) wave_sort_list<4>(s, L, lane);
+  else wave_sort_list<8>(s, L, lane);
+}
+
+// W waves per list of lo < L <= 512 W keys: each wave sorts its 512-key
+// chunk in registers, then the merges of size 1024 .. 512 W pair waves
+// through LDS (mirror and half-cleaners of 512 and more), registers
+// (256 .. 64) and lanes (32 .. 1).
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __restrict__ keys,
+                                                          const unsigned int* __restrict__ tile_start,
+                                                          const unsigned int* __restrict__ order, int lo,
+                                                          const Status* st) {
+  __shared__ unsigned long long sx[W * 512];
+  if (st->view_overflow) return;
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  const unsigned int start = tile_start[tile];
+  const int L = (int)(tile_start[tile + 1] - start);
+  if (L <= lo || L > 512 * W) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned long long* s = keys + start;
+  unsigned long long v[8];
+#pragma clang loop unroll(full)
+  for (int r = 0; r < 8; ++r) {
+    const int e = wave * 512 + r * 64 + lane;
+    v[r] = e < L ? s[e] : ~0ull;
+  }
+  const int rr = min(8, max(0, (L - wave * 512 + 63) >> 6));
+  wave_sort_regs<8>(v, 512, rr, lane);
+  for (int k = 1024; k <= 512 * W; k <<= 1) {
+    for (int j = k >> 1; j >= 512; j >>= 1) {  // j = k/2: mirror (partner e ^ (k - 1)); else e ^ j
+      const bool mirror = j == (k >> 1);
+      const int pw = mirror ? (wave ^ ((k >> 9) - 1)) : (wave ^ (j >> 9));
+      const bool lower = wave < pw;
+#pragma clang loop unroll(full)
+      for (int r = 0; r < 8; ++r) sx[wave * 512 + r * 64 + lane] = v[r];
+      __syncthreads();
+#pragma clang loop unroll(full)
+      for (int r = 0; r < 8; ++r) {
+        const unsigned long long w = mirror ? sx[pw * 512 + (r ^ 7) * 64 + (lane ^ 63)] : sx[pw * 512 + r * 64 + lane];
+        const bool take = lower ? (w < v[r]) : (w > v[r]);
+        v[r] = take ? w : v[r];
+      }
+      __syncthreads();
+    }
+    wave_reg_stage<8, 4>(v, 8);
+    wave_reg_stage<8, 2>(v, 8);
+    wave_reg_stage<8, 1>(v, 8);
+    wave_cross_cleaners<8>(v, 32, 8, lane);
+  }
+#pragma clang loop unroll(full)
+  for (int r = 0; r < 8; ++r) {
+    const int e = wave * 512 + r * 64 + lane;
+    if (e < L) s[e] = v[r];
+  }
+}
+
 static CullRecords cull_of(const BinArgs& a) {
   CullRecords c{};
   c.n = std::min(a.n_cull_records, 4);
@@ -681,15 +883,16 @@ static void sort_lists(const BinArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.tile_order, a.status);
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
                      a.status);
-  if (a.n_tiles > 0) {            // size classes 2..128, 129..256, ..., 2049..4096 (= kSortCap)
+  if (a.n_tiles > 0) {            // 2 .. 512 keys: one wave per list; .. 2048: 2 or 4 waves; .. 4096 (= kSortCap)
     unsigned long long* k = a.keys[a.sorted];
     const dim3 g(a.n_tiles);
-    hipLaunchKernelGGL((k_sort_blocks<64, 2>), g, dim3(64), 0, s, k, a.tile_start, 1, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<64, 4>), g, dim3(64), 0, s, k, a.tile_start, 128, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<64, 8>), g, dim3(64), 0, s, k, a.tile_start, 256, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<128, 8>), g, dim3(128), 0, s, k, a.tile_start, 512, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<256, 8>), g, dim3(256), 0, s, k, a.tile_start, 1024, a.status);
-    hipLaunchKernelGGL((k_sort_blocks<512, 8>), g, dim3(512), 0, s, k, a.tile_start, 2048, a.status);
+    hipLaunchKernelGGL(k_sort_lists_wave, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, k, a.tile_start,
+                       a.tile_order, a.n_tiles, a.status);
+    hipLaunchKernelGGL(k_sort_lists_wg<2>, g, dim3(128), 0, s, k, a.tile_start, a.tile_order, kWaveSortMax,
+                       a.status);
+    hipLaunchKernelGGL(k_sort_lists_wg<4>, g, dim3(256), 0, s, k, a.tile_start, a.tile_order, 2 * kWaveSortMax,
+                       a.status);
+    hipLaunchKernelGGL((k_sort_blocks<512, 8>), g, dim3(512), 0, s, k, a.tile_start, kWgSortMax, a.status);
   }
 }
 
