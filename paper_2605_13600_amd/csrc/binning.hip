@@ -24,7 +24,7 @@
 
 namespace scoup {
 
-constexpr int kCountThreads = 512;
+constexpr int kCountThreads = 1024;
 constexpr int kCountGroups = 256;          // workgroups of the counting pass (at least)
 constexpr int kCountMaxTiles = 49152;      // 16-bit LDS counters: 96 KB
 
@@ -403,12 +403,7 @@ __global__ __launch_bounds__(256) void k_bin_big(const unsigned int* __restrict_
   if (tile_start[t + 1] - tile_start[t] > (unsigned int)sort_cap) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
 }
 
-hipError_t binning_set_lds_limits() {
-  const int bytes = (int)sizeof(unsigned int) * (kCountMaxTiles / 2);
-  hipError_t e = hipFuncSetAttribute((const void*)k_bin_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
+
 
 int count_groups(long long n) {
   const long long need = (n + 65534) / 65535;              // at most 65535 Gaussians per 16-bit counter
@@ -633,10 +628,13 @@ long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
 // clamped length.
 constexpr int kOrderBuckets = 2048;
 
+constexpr int kOrderLdsTiles = 32768;          // bucket of each tile kept in LDS up to this many tiles
+
 __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restrict__ tile_start, int n_tiles,
                                                      unsigned int* __restrict__ order, const Status* st) {
   __shared__ unsigned int h[kOrderBuckets];
   __shared__ unsigned int part[1024];
+  extern __shared__ unsigned short s_b[];      // [n_tiles] when n_tiles <= kOrderLdsTiles
   const int tid = threadIdx.x;
   if (st->view_overflow) {
     for (int t = tid; t < n_tiles; t += 1024) order[t] = (unsigned int)t;
@@ -648,7 +646,12 @@ __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restr
     const unsigned int L = tile_start[t + 1] - tile_start[t];
     return kOrderBuckets - 1 - (int)min(L, (unsigned int)(kOrderBuckets - 1));
   };
-  for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&h[bucket(t)], 1u);
+  const bool keep = n_tiles <= kOrderLdsTiles;
+  for (int t = tid; t < n_tiles; t += 1024) {
+    const int b = bucket(t);
+    if (keep) s_b[t] = (unsigned short)b;
+    atomicAdd(&h[b], 1u);
+  }
   __syncthreads();
   // exclusive scan of the buckets: two per thread, then across threads
   const unsigned int c0 = h[2 * tid], c1 = h[2 * tid + 1];
@@ -665,7 +668,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const unsigned int* __restr
   h[2 * tid] = before;
   h[2 * tid + 1] = before + c0;
   __syncthreads();
-  for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[bucket(t)], 1u)] = (unsigned int)t;
+  for (int t = tid; t < n_tiles; t += 1024) order[atomicAdd(&h[keep ? (int)s_b[t] : bucket(t)], 1u)] = (unsigned int)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -870,6 +873,16 @@ __global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __
   }
 }
 
+hipError_t binning_set_lds_limits() {
+  const int bytes = (int)sizeof(unsigned int) * (kCountMaxTiles / 2);
+  hipError_t e = hipFuncSetAttribute((const void*)k_bin_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(unsigned short) * kOrderLdsTiles);
+}
+
 static CullRecords cull_of(const BinArgs& a) {
   CullRecords c{};
   c.n = std::min(a.n_cull_records, 4);
@@ -880,7 +893,8 @@ static CullRecords cull_of(const BinArgs& a) {
 // depth order inside every tile list of the sorted buffer
 static void sort_lists(const BinArgs& a, hipStream_t s) {
   if (a.tile_order && a.n_tiles > 0)
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.tile_order, a.status);
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), a.n_tiles <= kOrderLdsTiles ? 2 * (size_t)a.n_tiles : 0, s,
+                       a.tile_start, a.n_tiles, a.tile_order, a.status);
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
                      a.status);
   if (a.n_tiles > 0) {            // 2 .. 512 keys: one wave per list; .. 2048: 2 or 4 waves; .. 4096 (= kSortCap)
