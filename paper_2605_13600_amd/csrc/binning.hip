@@ -6,13 +6,17 @@
 //                 number of overlapped tiles n_i
 //   scan          device-wide exclusive scan of n_i -> Gaussian-major pair
 //                 offsets off_i (also the record slots of the uplift)
-//   k_bin_count / k_bin_colscan / tile scan / k_bin_place
+//   k_bin_count / k_bin_colscan / k_tile_scan_order / k_bin_place
 //                 pairs grouped by tile in one counting pass: key (float32
 //                 depth bits << 32 | i) of pair (i, t) placed in t's list,
-//                 tile t owns [tile_start[t], tile_start[t+1])
-//   (larger images: k_emit + stable LSD radix sort by tile id + k_tile_ranges)
-//   k_sort_blocks each block list of at most kSortCap pairs sorted by (depth,
-//                 id) in LDS, one workgroup per block
+//                 tile t owns [tile_start[t], tile_start[t+1]); the tile
+//                 order for the compositing (longest list first)
+//   (larger images: k_emit + stable LSD radix sort by tile id + k_tile_ranges
+//    + k_tile_order)
+//   k_sort_lists_wave / k_sort_lists_wg / k_sort_blocks
+//                 each block list sorted by (depth, id): one wave in registers
+//                 up to 512 pairs, 2 or 4 waves up to 2048, one workgroup in
+//                 LDS up to kSortCap
 //   k_sort_big    lists longer than kSortCap sorted in global memory
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -394,14 +398,6 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
   }
 }
 
-// tiles longer than sort_cap go to k_sort_big
-__global__ __launch_bounds__(256) void k_bin_big(const unsigned int* __restrict__ tile_start, int n_tiles,
-                                                 int sort_cap, unsigned int* __restrict__ big_tiles, Status* st) {
-  if (st->view_overflow) return;
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_tiles) return;
-  if (tile_start[t + 1] - tile_start[t] > (unsigned int)sort_cap) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
-}
 
 
 
@@ -873,14 +869,74 @@ __global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __
   }
 }
 
+// Counting path, one workgroup: exclusive scan of the block list lengths
+// (tile_start holds the lengths on entry, the starts on exit), the lists
+// longer than sort_cap (big_tiles), and the compositing order, longest list
+// first (as k_tile_order).  Thread i owns tiles [i c, i c + c): it reads
+// its lengths, and after the scan of the 1024 chunk sums rewrites them as
+// starts, keeping each tile's length bucket in LDS for the placement.
+__global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restrict__ tile_start, int n_tiles,
+                                                          int sort_cap, unsigned int* __restrict__ big_tiles,
+                                                          unsigned int* __restrict__ order, Status* st) {
+  __shared__ unsigned int h[kOrderBuckets];
+  __shared__ unsigned int part[1024];
+  extern __shared__ unsigned short s_b[];      // [n_tiles] length buckets
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kOrderBuckets; b += 1024) h[b] = 0u;
+  const int c = (n_tiles + 1023) / 1024;
+  const int t0 = min(n_tiles, tid * c), t1 = min(n_tiles, t0 + c);
+  unsigned int sum = 0u;
+  for (int t = t0; t < t1; ++t) sum += tile_start[t];
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned int v = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  unsigned int run = part[tid] - sum;
+  for (int t = t0; t < t1; ++t) {
+    const unsigned int L = tile_start[t];
+    tile_start[t] = run;
+    run += L;
+    const int b = kOrderBuckets - 1 - (int)min(L, (unsigned int)(kOrderBuckets - 1));
+    s_b[t] = (unsigned short)b;
+    atomicAdd(&h[b], 1u);
+    if (L > (unsigned int)sort_cap && !st->view_overflow) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
+  }
+  if (tid == 1023) tile_start[n_tiles] = part[1023];
+  __syncthreads();
+  if (!order) return;
+  // exclusive scan of the buckets: two per thread, then across threads
+  const unsigned int c0 = h[2 * tid], c1 = h[2 * tid + 1];
+  part[tid] = c0 + c1;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned int v = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  const unsigned int before = part[tid] - (c0 + c1);
+  __syncthreads();
+  h[2 * tid] = before;
+  h[2 * tid + 1] = before + c0;
+  __syncthreads();
+  for (int t = t0; t < t1; ++t) order[atomicAdd(&h[s_b[t]], 1u)] = (unsigned int)t;
+}
+
 hipError_t binning_set_lds_limits() {
   const int bytes = (int)sizeof(unsigned int) * (kCountMaxTiles / 2);
   hipError_t e = hipFuncSetAttribute((const void*)k_bin_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(unsigned short) * kOrderLdsTiles);
+  e = hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)sizeof(unsigned short) * kOrderLdsTiles);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_tile_scan_order, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sizeof(unsigned short) * kCountMaxTiles);
 }
 
 static CullRecords cull_of(const BinArgs& a) {
@@ -891,8 +947,8 @@ static CullRecords cull_of(const BinArgs& a) {
 }
 
 // depth order inside every tile list of the sorted buffer
-static void sort_lists(const BinArgs& a, hipStream_t s) {
-  if (a.tile_order && a.n_tiles > 0)
+static void sort_lists(const BinArgs& a, hipStream_t s, bool order_done) {
+  if (a.tile_order && a.n_tiles > 0 && !order_done)
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), a.n_tiles <= kOrderLdsTiles ? 2 * (size_t)a.n_tiles : 0, s,
                        a.tile_start, a.n_tiles, a.tile_order, a.status);
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
@@ -946,18 +1002,13 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, a.bin_hist, a.status);
     hipLaunchKernelGGL(k_bin_colscan, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.bin_hist, nwg, a.n_tiles,
                        a.tile_start, a.status);
-    const int tsb = (int)scan_blocks(a.n_tiles);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, a.scan_part, tsb, 0ull, (Status*)nullptr);
-    hipLaunchKernelGGL(k_scan_down, dim3(tsb), dim3(256), 0, s, a.tile_start, (long long)a.n_tiles, a.scan_part,
-                       a.tile_start + a.n_tiles);
+    hipLaunchKernelGGL(k_tile_scan_order, dim3(1), dim3(1024), sizeof(unsigned short) * (size_t)a.n_tiles, s,
+                       a.tile_start, a.n_tiles, a.sort_cap, a.big_tiles, a.tile_order, a.status);
     hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, (const unsigned int*)a.bin_hist,
                        (const unsigned int*)a.tile_start, a.keys[0], a.status);
-    hipLaunchKernelGGL(k_bin_big, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.tile_start, a.n_tiles,
-                       a.sort_cap, a.big_tiles, a.status);
     a.sorted = 0;
-    sort_lists(a, s);
+    sort_lists(a, s, true);
     StageTimer::end(kStSortBig, s);
     return hipGetLastError();
   }
@@ -982,7 +1033,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
   a.sorted = cur;
   hipLaunchKernelGGL(k_tile_ranges, dim3((a.n_tiles + 1 + 255) / 256), dim3(256), 0, s, a.tile_ids[cur],
                      a.n_tiles, a.tile_start, a.sort_cap, a.big_tiles, a.status);
-  sort_lists(a, s);
+  sort_lists(a, s, false);
   StageTimer::end(kStSortBig, s);
   return hipGetLastError();
 }

@@ -295,3 +295,27 @@ def test_dense_feature_uplift_fragmented():
     nrm = np.linalg.norm(f_ref, axis=1)
     err = np.linalg.norm(fg - f_ref, axis=1)
     assert (err[ok] <= 1e-5 * nrm[ok] + 1e-7).all(), float((err[ok] / np.maximum(nrm[ok], 1e-30)).max())
+
+
+@pytest.mark.parametrize("n", [2, 64, 65, 128, 129, 256, 257, 512, 513, 1024, 1025, 2048, 2049, 4096, 4097])
+def test_block_list_lengths_at_sort_class_edges(n):
+    """One 8x8 block whose list holds exactly n pairs (every Gaussian covers
+    the whole block), for n at the edges of the depth sort's size classes
+    (one wave, two and four waves, one workgroup, global memory).  Opacities
+    near 1/255 keep every pixel compositing through ~1800 Gaussians, so the
+    weight of each one depends on the exact depth order before it; a tenth
+    of the Gaussians repeat another's position (equal depths, id order)."""
+    require_gpu()
+    rng = np.random.default_rng(4000 + n)
+    means = np.stack([rng.uniform(-0.05, 0.05, n), rng.uniform(-0.05, 0.05, n), rng.uniform(1.0, 3.0, n)], 1)
+    dup = rng.random(n) < 0.1
+    dup[0] = False
+    means[dup] = means[rng.integers(0, n, int(dup.sum()))]
+    g = S.gaussians(means, np.log(30.0), rng.uniform(0.0045, 0.0055, n))
+    cam = S.axis_camera(8, 8, 10.0)
+    rm = np.zeros((8, 8), np.int32)
+    rm[:, 4:] = 1
+    idx, val = sg.region_codes(np.random.default_rng(2), 2, 16, 4)
+    v = S.views_for([cam], [rm], idx, val, 16)
+    sa, st, ref = _compare(g, v, 4, f"list{n}")
+    assert ref.n_contrib >= 64 * min(n, 1800)
