@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 not used
 STAGES = ["project", "pair_scan", "emit", "tile_sort", "composite", "topk",
-          "render", "decode", "render_backward", "backward_gemm", "row_build", "relevancy", "relevancy_fold"]
+          "render", "decode", "render_backward", "backward_gemm", "row_build", "relevancy", "relevancy_fold",
+          "extra_apply"]
 
 
 def log(msg):

@@ -278,6 +278,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
  *   0 project  1 pair scan  2 emit  3 tile sort  4 composite
  *   5 top-k    6 render     7 decode  8 render backward  9 backward GEMMs
  *   10 accumulator row build  11 relevancy  12 relevancy vector folding
+ *   13 deferred further-region entries added to the accumulator
  * Process-wide state; not meant for concurrent calls from several threads. */
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);

@@ -8,7 +8,7 @@
 namespace scoup {
 
 enum Stage { kStProject = 0, kStScan, kStEmit, kStSortBig, kStComposite, kStTopk, kStRender, kStDecode,
-             kStRenderBwd, kStBwdGemm, kStRowBuild, kStRelevancy, kStRelPrep, kNumStages };
+             kStRenderBwd, kStBwdGemm, kStRowBuild, kStRelevancy, kStRelPrep, kStApplyExtra, kNumStages };
 
 // Records a HIP event pair around each launch when stage timing is enabled.
 struct StageTimer {

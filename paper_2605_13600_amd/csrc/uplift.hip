@@ -487,44 +487,80 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   const unsigned int cap = (unsigned int)a.capacity;
   const bool vec = (a.k_code & 3) == 0 &&
                    ((reinterpret_cast<uintptr_t>(a.code_idx) | reinterpret_cast<uintptr_t>(a.code_val)) & 15) == 0;
-  for (int v = wave; v < a.n_views; v += 4) {
-    const unsigned int* offv = a.offsets + (long long)v * (a.n + 1) + i0;
-    const unsigned int ob = lane <= gn ? 2u * min(offv[lane], cap) : 0u;   // first record of Gaussian lane
-    const unsigned int r0 = (unsigned int)__builtin_amdgcn_readlane((int)ob, 0);
-    const unsigned int r1 = (unsigned int)__builtin_amdgcn_readlane((int)ob, gn);
-    const float2* recv = a.records + (long long)v * 2 * a.capacity;
-    for (unsigned int base = r0; base < r1; base += 64) {
-      const unsigned int r = base + (unsigned int)lane;
-      int g = 0;                               // last Gaussian whose range starts at or before r
-      for (int t = 1; t < gn; ++t) g = r >= (unsigned int)__builtin_amdgcn_readlane((int)ob, t) ? t : g;
-      if (r >= r1) continue;
-      const float2 rc = recv[r];
-      const int reg = __float_as_int(rc.x);
-      if (rc.y == 0.0f || reg < 0 || reg >= a.r_total) continue;
-      float* row = rows + g * stride;
-      const long long gr = (long long)reg * a.k_code;
-      for (int c = 0; c < a.k_code; c += 4) {     // four slots' loads before their adds
-        int jj[4];
-        float cv[4];
-        if (vec) {
-          const int4 ji = *reinterpret_cast<const int4*>(a.code_idx + gr + c);
-          const float4 jv = *reinterpret_cast<const float4*>(a.code_val + gr + c);
-          jj[0] = ji.x; jj[1] = ji.y; jj[2] = ji.z; jj[3] = ji.w;
-          cv[0] = jv.x; cv[1] = jv.y; cv[2] = jv.z; cv[3] = jv.w;
-        } else {
+  // first record of Gaussian `lane` (lanes 0..gn) in view v
+  auto load_ob = [&](int v) -> unsigned int {
+    if (v >= a.n_views || lane > gn) return 0u;
+    return 2u * min(a.offsets[(long long)v * (a.n + 1) + i0 + lane], cap);
+  };
+  auto load_rec = [&](int v, unsigned int r, unsigned int r1) -> float2 {
+    return (v < a.n_views && r < r1) ? a.records[(long long)v * 2 * a.capacity + r] : make_float2(0.0f, 0.0f);
+  };
+  // records of one 64-record chunk (record r of lane) into the rows.  Equal
+  // (Gaussian, region) records sit two lanes apart (the same slot of
+  // consecutive pairs): a segmented sum along lanes of equal parity folds
+  // each run of them, and the run's last lane adds its code once (fewer
+  // LDS atomics, which would otherwise collide on the same row entries).
+  auto add_chunk = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc) {
+    int g = 0;                                 // last Gaussian whose range starts at or before r
+    for (int t = 1; t < gn; ++t) g = r >= (unsigned int)__builtin_amdgcn_readlane((int)ob, t) ? t : g;
+    const int reg = __float_as_int(rc.x);
+    const bool valid = r < r1 && rc.y != 0.0f && reg >= 0 && reg < a.r_total;
+    const int gk = valid ? g : -1;
+    const int pg = __shfl_up(gk, 2, 64), pr = __shfl_up(reg, 2, 64);
+    bool head = !valid || lane < 2 || pg != gk || pr != reg;
+    float w = valid ? rc.y : 0.0f;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            jj[u] = c + u < a.k_code ? a.code_idx[gr + c + u] : -1;
-            cv[u] = c + u < a.k_code ? a.code_val[gr + c + u] : 0.0f;
-          }
-        }
+    for (int d = 2; d < 64; d <<= 1) {
+      const float wu = __shfl_up(w, d, 64);
+      const int hu = __shfl_up((int)head, d, 64);
+      if (lane >= d && !head) { w += wu; head = hu != 0; }
+    }
+    const int ng = __shfl_down(gk, 2, 64), nr = __shfl_down(reg, 2, 64);
+    if (!valid || (lane < 62 && ng == gk && nr == reg)) return;
+    float* row = rows + g * stride;
+    const long long gr = (long long)reg * a.k_code;
+    for (int c = 0; c < a.k_code; c += 4) {   // four slots' loads before their adds
+      int jj[4];
+      float cv[4];
+      if (vec) {
+        const int4 ji = *reinterpret_cast<const int4*>(a.code_idx + gr + c);
+        const float4 jv = *reinterpret_cast<const float4*>(a.code_val + gr + c);
+        jj[0] = ji.x; jj[1] = ji.y; jj[2] = ji.z; jj[3] = ji.w;
+        cv[0] = jv.x; cv[1] = jv.y; cv[2] = jv.z; cv[3] = jv.w;
+      } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
-          else if (jj[u] >= 0) atomicAdd(&row[jj[u]], rc.y * cv[u]);
+          jj[u] = c + u < a.k_code ? a.code_idx[gr + c + u] : -1;
+          cv[u] = c + u < a.k_code ? a.code_val[gr + c + u] : 0.0f;
         }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
+        else if (jj[u] >= 0) atomicAdd(&row[jj[u]], w * cv[u]);
+      }
     }
+  };
+  // wave w walks views w, w+4, ...; the next view's offsets are loaded two
+  // views ahead and its first 64 records one view ahead of their use
+  int v = wave;
+  unsigned int ob_c = load_ob(v), ob_n = load_ob(v + 4);
+  unsigned int r0_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, 0);
+  unsigned int r1_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, gn);
+  float2 rc_c = load_rec(v, r0_c + (unsigned int)lane, r1_c);
+  for (; v < a.n_views; v += 4) {
+    const unsigned int ob_nn = load_ob(v + 8);
+    const unsigned int r0_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, 0);
+    const unsigned int r1_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, gn);
+    const float2 rc_n = load_rec(v + 4, r0_n + (unsigned int)lane, r1_n);
+    add_chunk(ob_c, r0_c + (unsigned int)lane, r1_c, rc_c);
+    for (unsigned int base = r0_c + 64u; base < r1_c; base += 64u) {
+      const unsigned int r = base + (unsigned int)lane;
+      add_chunk(ob_c, r, r1_c, load_rec(v, r, r1_c));
+    }
+    ob_c = ob_n; ob_n = ob_nn;
+    r0_c = r0_n; r1_c = r1_n;
+    rc_c = rc_n;
   }
   __syncthreads();
   for (int j = tid; j < gn * M; j += 256) acc[j] = rows[(j / M) * stride + (j % M)];
@@ -686,10 +722,13 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
-  if (a.extra_cap > 0)
+  StageTimer::end(kStComposite, s);
+  if (a.extra_cap > 0) {
+    StageTimer::begin(kStApplyExtra, s);
     hipLaunchKernelGGL(k_apply_extra, dim3(std::min(2048u, (a.extra_cap + 255) / 256)), dim3(256), 0, s, a,
                        a.m_atoms, b.status);
-  StageTimer::end(kStComposite, s);
+    StageTimer::end(kStApplyExtra, s);
+  }
   return hipGetLastError();
 }
 
