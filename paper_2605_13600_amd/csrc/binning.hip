@@ -31,6 +31,7 @@ namespace scoup {
 constexpr int kCountThreads = 1024;
 constexpr int kCountGroups = 256;          // workgroups of the counting pass (at least)
 constexpr int kCountMaxTiles = 49152;      // 16-bit LDS counters: 96 KB
+constexpr int kCountPlaceLdsTiles = 24576;  // placing pass: tile starts + bases in LDS up to here (96 KB more)
 
 // the uplift's record arrays of the current view, per level (pairs whose
 // block the Gaussian cannot reach are never composited: zero records)
@@ -56,7 +57,13 @@ __global__ __launch_bounds__(256) void k_project(
   s.depth_bits = 0u; s.live = 0u;
   unsigned int nt = 0;
 
+  // every input is loaded up front: one memory latency per thread, not one per use
   const double mx = means[3 * i + 0], my = means[3 * i + 1], mz = means[3 * i + 2];
+  const float o_in = opacities[i];
+  const float q_in[4] = {quats[4 * i + 0], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+  const float ls_in[3] = {log_scales[3 * i + 0], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+  asm volatile("" ::"v"(o_in), "v"(q_in[0]), "v"(q_in[1]), "v"(q_in[2]), "v"(q_in[3]), "v"(ls_in[0]),
+               "v"(ls_in[1]), "v"(ls_in[2]));   // keeps the loads ahead of the visibility test
   double x, y, z;
   {
     // Camera point p = R mu + t summed left to right without fused multiply-adds,
@@ -66,21 +73,19 @@ __global__ __launch_bounds__(256) void k_project(
     y = (double)cam.R[3] * mx + (double)cam.R[4] * my + (double)cam.R[5] * mz + (double)cam.t[1];
     z = (double)cam.R[6] * mx + (double)cam.R[7] * my + (double)cam.R[8] * mz + (double)cam.t[2];
   }
-  const double o = opacities[i];
+  const double o = o_in;
   const double lo = log(255.0 * o);
   if (!(z > (double)cam.near_z) || !(lo >= 0.0)) { out[i] = s; n_tiles[i] = 0u; return; }
 
   // 3D covariance Sigma = R diag(exp(2 s)) R^T from the normalised quaternion
-  double qw = quats[4 * i + 0], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  double qw = q_in[0], qx = q_in[1], qy = q_in[2], qz = q_in[3];
   const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= qn; qx *= qn; qy *= qn; qz *= qn;
   const double Rq[3][3] = {
       {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
       {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
       {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  const double s2[3] = {exp(2.0 * (double)log_scales[3 * i + 0]),
-                        exp(2.0 * (double)log_scales[3 * i + 1]),
-                        exp(2.0 * (double)log_scales[3 * i + 2])};
+  const double s2[3] = {exp(2.0 * (double)ls_in[0]), exp(2.0 * (double)ls_in[1]), exp(2.0 * (double)ls_in[2])};
   double S[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -371,12 +376,16 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
                                                              const unsigned int* __restrict__ tile_start,
                                                              unsigned long long* __restrict__ keys,
                                                              const Status* st) {
-  extern __shared__ unsigned int h[];
-  if (st->view_overflow) return;
-  const int nw = (n_tiles + 1) >> 1;
-  for (int j = threadIdx.x; j < nw; j += kCountThreads) h[j] = 0u;
-  __syncthreads();
+  extern __shared__ unsigned int h[];         // tickets: ceil(n_tiles / 2) words, then (images
+  if (st->view_overflow) return;               // up to kCountPlaceLdsTiles blocks) start + base
+  const int nw = (n_tiles + 1) >> 1;           // of every block: n_tiles words
+  const bool staged = n_tiles <= kCountPlaceLdsTiles;
+  unsigned int* sb = h + nw;
   const unsigned int* base = hist + (long long)blockIdx.x * n_tiles;
+  for (int j = threadIdx.x; j < nw; j += kCountThreads) h[j] = 0u;
+  if (staged)
+    for (int t = threadIdx.x; t < n_tiles; t += kCountThreads) sb[t] = tile_start[t] + base[t];
+  __syncthreads();
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
   for (long long i = i0 + threadIdx.x; i < i1; i += kCountThreads) {
@@ -393,7 +402,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
         const int t = ty * tiles_x + tx;
         const unsigned int sh = 16 * (t & 1);
         const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
-        keys[tile_start[t] + base[t] + ticket] = key;
+        keys[(staged ? sb[t] : tile_start[t] + base[t]) + ticket] = key;
       }
   }
 }
@@ -930,7 +939,9 @@ hipError_t binning_set_lds_limits() {
   const int bytes = (int)sizeof(unsigned int) * (kCountMaxTiles / 2);
   hipError_t e = hipFuncSetAttribute((const void*)k_bin_count, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  // placing pass: 2 B of tickets + 4 B of start per block while staged (6 x 24576 B), else tickets only
+  e = hipFuncSetAttribute((const void*)k_bin_place, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          std::max(bytes, 6 * kCountPlaceLdsTiles));
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sizeof(unsigned short) * kOrderLdsTiles);
@@ -1004,7 +1015,9 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
                        a.tile_start, a.status);
     hipLaunchKernelGGL(k_tile_scan_order, dim3(1), dim3(1024), sizeof(unsigned short) * (size_t)a.n_tiles, s,
                        a.tile_start, a.n_tiles, a.sort_cap, a.big_tiles, a.tile_order, a.status);
-    hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
+    const size_t lds_place = lds + (a.n_tiles <= kCountPlaceLdsTiles ? sizeof(unsigned int) * (size_t)a.n_tiles : 0);
+    hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds_place, s,
+                       a.splats, a.n, a.tiles_x, a.n_tiles,
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, (const unsigned int*)a.bin_hist,
                        (const unsigned int*)a.tile_start, a.keys[0], a.status);
     a.sorted = 0;
