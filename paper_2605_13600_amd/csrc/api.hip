@@ -45,7 +45,7 @@ struct BinLayout {
   bool counting;
 };
 
-BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int rec_views) {
+BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int rec_views, bool extra_entries) {
   BinLayout L{};
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   size_t off = 0;
@@ -68,7 +68,7 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
   L.keys[1] = off; off = align256(off + 8 * (size_t)cap);
   L.records = off; off = align256(off + 16 * (size_t)cap * (size_t)rec_views);
   // uplift: deferred weights of regions beyond a block's two record regions (one view at a time)
-  L.extra_cap = rec_views > 0 ? (unsigned int)std::max<int64_t>(1 << 18, std::min<int64_t>(cap / 16, 1 << 26)) : 0u;
+  L.extra_cap = extra_entries ? (unsigned int)std::max<int64_t>(1 << 18, std::min<int64_t>(cap / 16, 1 << 26)) : 0u;
   L.extra = off; off = align256(off + 16 * (size_t)L.extra_cap);
   L.total = off;
   return L;
@@ -76,10 +76,10 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
 
 // largest pair capacity whose single-view layout fits in `bytes` (0 if none)
 int64_t capacity_for(int64_t n, int max_tiles, size_t bytes) {
-  const size_t fixed = bin_layout(n, max_tiles, 0, 1, 0).total;
+  const size_t fixed = bin_layout(n, max_tiles, 0, 1, 0, false).total;
   if (bytes <= fixed + 8192) return 0;
   int64_t cap = (int64_t)(((bytes - fixed - 8192) * 8) / 197);
-  while (cap > 0 && bin_layout(n, max_tiles, cap, 1, 0).total > bytes) cap -= 64;
+  while (cap > 0 && bin_layout(n, max_tiles, cap, 1, 0, false).total > bytes) cap -= 64;
   return std::min<int64_t>(std::max<int64_t>(cap, 0), 0x7fffffffLL);
 }
 
@@ -87,6 +87,42 @@ int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
   int mt = 1;
   for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height, 3));
   return mt;
+}
+
+// The uplift keeps two views in flight (binning of one overlapping the
+// compositing of the other) when a view batch holds two or more views: a
+// second set of per-view binning buffers follows the first layout.
+BinLayout uplift_layout(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
+  return bin_layout(n, mt, cap, vb, vb * n_levels, true);
+}
+BinLayout uplift_lane2_layout(int64_t n, int mt, int64_t cap) { return bin_layout(n, mt, cap, 0, 0, true); }
+size_t uplift_layout_total(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
+  const size_t t = uplift_layout(n, mt, cap, vb, n_levels).total;
+  return vb >= 2 ? align256(t) + uplift_lane2_layout(n, mt, cap).total : t;
+}
+
+// The library's second stream on the current device (default priority), and
+// events ordering it against the caller's stream; created on first use.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[3] = {};
+};
+std::mutex g_side_mu;
+SideStream g_side[64];
+hipError_t side_stream(SideStream** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SideStream& ss = g_side[dev];
+  if (!ss.s) {
+    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) { ss.s = nullptr; return e; }
+    for (int k = 0; k < 3; ++k)
+      if ((e = hipEventCreateWithFlags(&ss.ev[k], hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *out = &ss;
+  return hipSuccess;
 }
 
 void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const BinLayout& L, long long capacity,
@@ -259,7 +295,7 @@ size_t scoup_uplift_levels_workspace_bytes(int64_t n_gaussians, int32_t n_levels
   if (views->n_views > 0 && !views->cams) return 0;
   if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(6 * n_gaussians, 1 << 16);
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : views->n_views, views->n_views));
-  return bin_layout(n_gaussians, max_tiles_of(views), pair_capacity, vb, vb * n_levels).total;
+  return uplift_layout_total(n_gaussians, max_tiles_of(views), pair_capacity, vb, n_levels);
 }
 
 namespace {
@@ -294,34 +330,54 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : std::max(1, v->n_views),
                                            std::max(1, v->n_views)));
   const int mt = max_tiles_of(v);
-  const BinLayout L = bin_layout(g->n, mt, pair_capacity, vb, vb * n_levels);
-  if (ws_bytes < L.total) {
+  const BinLayout L = uplift_layout(g->n, mt, pair_capacity, vb, n_levels);
+  const int lanes = vb >= 2 ? 2 : 1;          // views in flight
+  const size_t need = uplift_layout_total(g->n, mt, pair_capacity, vb, n_levels);
+  if (ws_bytes < need) {
     g_required_pairs = pair_capacity;
     return fail(SCOUP_E_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
-                                       std::to_string(L.total) + " this capacity and view batch need");
+                                       std::to_string(need) + " this capacity and view batch need");
   }
   HIP_TRY(ensure_lds_limits());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SideStream* side = nullptr;
+  if (lanes == 2) HIP_TRY(side_stream(&side));
   char* base = static_cast<char*>(ws);
-  Status* status = reinterpret_cast<Status*>(base + L.status);
-  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  const BinLayout L2 = uplift_lane2_layout(g->n, mt, pair_capacity);
+  char* base2 = base + align256(L.total);
+  Status* status[2] = {reinterpret_cast<Status*>(base + L.status),
+                       lanes == 2 ? reinterpret_cast<Status*>(base2 + L2.status) : nullptr};
+  for (int k = 0; k < lanes; ++k) HIP_TRY(hipMemsetAsync(status[k], 0, sizeof(Status), s));
   const size_t acc_bytes = sizeof(float) * (size_t)g->n * (size_t)v->m_atoms;
   if (!accumulate && acc_bytes)
     for (int l = 0; l < n_levels; ++l) HIP_TRY(hipMemsetAsync(acc[l], 0, acc_bytes, s));
 
-  UpliftViewArgs a{};
-  BinArgs& b = a.bin;
-  fill_bin(b, g, base, L, pair_capacity, 3, kSortCap);
-  a.n_levels = n_levels;
-  a.m_atoms = v->m_atoms;
-  a.extra = reinterpret_cast<float4*>(base + L.extra);
-  a.extra_cap = L.extra_cap;
-  unsigned int* off_all = b.offsets;
+  // lane k: binning buffers, status and deferred entries of the views it handles; views
+  // alternate between the lanes, lane 0 on the caller's stream, lane 1 on the side stream
+  UpliftViewArgs a[2] = {};
+  fill_bin(a[0].bin, g, base, L, pair_capacity, 3, kSortCap);
+  a[0].extra = reinterpret_cast<float4*>(base + L.extra);
+  a[0].extra_cap = L.extra_cap;
+  if (lanes == 2) {
+    fill_bin(a[1].bin, g, base2, L2, pair_capacity, 3, kSortCap);
+    a[1].extra = reinterpret_cast<float4*>(base2 + L2.extra);
+    a[1].extra_cap = L2.extra_cap;
+  }
+  unsigned int* off_all = a[0].bin.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
   const size_t rec_view = 2 * (size_t)pair_capacity;           // float2 per view and level
-  for (int l = 0; l < n_levels; ++l) {
-    a.lv[l].code_idx = lvs[l].code_idx; a.lv[l].code_val = lvs[l].code_val;
-    a.lv[l].k_code = lvs[l].k_code; a.lv[l].acc = acc[l];
+  for (int k = 0; k < lanes; ++k) {
+    a[k].n_levels = n_levels;
+    a[k].m_atoms = v->m_atoms;
+    for (int l = 0; l < n_levels; ++l) {
+      a[k].lv[l].code_idx = lvs[l].code_idx; a[k].lv[l].code_val = lvs[l].code_val;
+      a[k].lv[l].k_code = lvs[l].k_code; a[k].lv[l].acc = acc[l];
+    }
+  }
+  hipStream_t strm[2] = {s, side ? side->s : s};
+  if (lanes == 2) {                            // lane 1 starts after the clears above
+    HIP_TRY(hipEventRecord(side->ev[0], s));
+    HIP_TRY(hipStreamWaitEvent(side->s, side->ev[0], 0));
   }
   const bool want_topk = k_top > 0;
   if (g->n > 0) {
@@ -329,6 +385,8 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
       const int nvb = std::min(vb, v->n_views - v0);
       for (int j = 0; j < nvb; ++j) {
         const int i = v0 + j;
+        UpliftViewArgs& av = a[j % lanes];
+        BinArgs& b = av.bin;
         const scoup_camera& c = v->cams[i];
         b.cam = to_dev(c);
         b.tiles_x = (c.width + 7) / 8;
@@ -336,13 +394,17 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         b.offsets = off_all + (size_t)j * (size_t)(g->n + 1);
         b.n_cull_records = n_levels;
         for (int l = 0; l < n_levels; ++l) {
-          a.lv[l].records = rec_all + ((size_t)l * vb + j) * rec_view;
-          b.cull_records[l] = a.lv[l].records;
-          a.lv[l].rmap = lvs[l].region_maps + lvs[l].map_offsets[i];
-          a.lv[l].n_regions = (int)(lvs[l].region_base[i + 1] - lvs[l].region_base[i]);
-          a.lv[l].region_base = lvs[l].region_base[i];
+          av.lv[l].records = rec_all + ((size_t)l * vb + j) * rec_view;
+          b.cull_records[l] = av.lv[l].records;
+          av.lv[l].rmap = lvs[l].region_maps + lvs[l].map_offsets[i];
+          av.lv[l].n_regions = (int)(lvs[l].region_base[i + 1] - lvs[l].region_base[i]);
+          av.lv[l].region_base = lvs[l].region_base[i];
         }
-        HIP_TRY(launch_uplift_view(a, s));
+        HIP_TRY(launch_uplift_view(av, strm[j % lanes]));
+      }
+      if (lanes == 2) {                        // the row build reads the records of both lanes
+        HIP_TRY(hipEventRecord(side->ev[1], side->s));
+        HIP_TRY(hipStreamWaitEvent(s, side->ev[1], 0));
       }
       const bool last = v0 + vb >= v->n_views;
       for (int l = 0; l < n_levels; ++l) {
@@ -351,13 +413,17 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         rb.code_idx = lvs[l].code_idx; rb.code_val = lvs[l].code_val;
         rb.r_total = lvs[l].region_base[v->n_views];
         rb.offsets = off_all; rb.records = rec_all + (size_t)l * vb * rec_view; rb.capacity = pair_capacity;
-        rb.acc = acc[l]; rb.status = status;
+        rb.acc = acc[l]; rb.status = status[0];
         rb.n_views = nvb;
         rb.k_top = (want_topk && last) ? k_top : 0;
         rb.topk_idx = want_topk ? topk_idx[l] : nullptr;
         rb.topk_val = want_topk ? topk_val[l] : nullptr;
         rb.entropy = (entropy && last) ? entropy[l] : nullptr;
         HIP_TRY(launch_rowbuild(rb, s));
+      }
+      if (lanes == 2 && !last) {               // the next batch reuses the records and offsets
+        HIP_TRY(hipEventRecord(side->ev[2], s));
+        HIP_TRY(hipStreamWaitEvent(side->s, side->ev[2], 0));
       }
     }
     if (v->n_views == 0)
@@ -366,11 +432,16 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         if (entropy && entropy[l]) HIP_TRY(launch_entropy(acc[l], g->n, v->m_atoms, entropy[l], s));
       }
   }
-  if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
-  Status h{};
-  HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  Status h{}, h2{};
+  for (int k = 0; k < lanes; ++k) {
+    if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status[k], s));
+    HIP_TRY(hipMemcpyAsync(k ? &h2 : &h, status[k], sizeof(Status), hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   StageTimer::collect();
+  h.any_overflow |= h2.any_overflow;
+  h.max_pairs = std::max(h.max_pairs, h2.max_pairs);
+  h.data_error |= h2.data_error;
   if (h.any_overflow) {
     g_required_pairs = (int64_t)h.max_pairs;
     return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(pair_capacity) + " exceeded; need " +
@@ -440,7 +511,7 @@ scoup_status scoup_uplift_dense(const scoup_gaussians* g, const scoup_views* v, 
   const size_t fbytes = align256(4 * (size_t)rt * (size_t)dim);
   const int vb = std::max(1, std::min<int>(view_batch > 0 ? view_batch : std::max(1, v->n_views),
                                            std::max(1, v->n_views)));
-  const BinLayout L = bin_layout(g->n, max_tiles_of(v), pair_capacity, vb, vb);
+  const BinLayout L = bin_layout(g->n, max_tiles_of(v), pair_capacity, vb, vb, true);
   if (ws_bytes < fbytes + L.total) {
     g_required_pairs = pair_capacity;
     return fail(SCOUP_E_WORKSPACE, "workspace too small for this capacity and view batch");
@@ -538,7 +609,7 @@ scoup_status scoup_uplift(const scoup_gaussians* g, const scoup_views* v, int32_
 size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int64_t pair_capacity) {
   if (!cam || n_gaussians < 0) return 0;
   if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(8 * n_gaussians, 1 << 16);
-  return bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3), pair_capacity, 1, 0).total;
+  return bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3), pair_capacity, 1, 0, false).total;
 }
 
 scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
@@ -566,7 +637,7 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
     g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
   }
-  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0);
+  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0, false);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   RenderViewArgs a{};
@@ -704,7 +775,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
     g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
   }
-  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0);
+  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0, false);
   char* base = static_cast<char*>(ws);
   void* prep = base;
   float* dW = reinterpret_cast<float*>(base + prep_b);
