@@ -321,6 +321,9 @@ def main():
     ap.add_argument("--extras", type=int, default=1,
                     help="three-level pass and dense-vs-sparse uplift sections (0 = skip)")
     ap.add_argument("--backward", type=int, default=1, help="time the render + decode backward (0 = skip)")
+    ap.add_argument("--views-in-flight", type=int, default=4,
+                    help="views projected, binned and composited at once in the timed steps (1..4); the "
+                         "per-stage timing step always runs one view at a time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling HBM counters in a profile)")
     args = ap.parse_args()
@@ -356,6 +359,7 @@ def main():
         idx, val, a, nc = P.uplift(dg, dv, k, workspace=ws, acc=acc)
         return nc
 
+    P.set_views_in_flight(args.views_in_flight)
     for i in range(args.warmup):
         nc = step()
         log(f"warmup {i} done, contributions {nc}")
@@ -368,9 +372,12 @@ def main():
     ms = dt * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms:.2f} ms/step, {nc} contributions/step")
 
-    # per-stage kernel time with HIP events on the launch stream (one extra step)
+    # per-stage kernel time with HIP events on the launch stream (one extra step,
+    # one view at a time, so that every kernel's events time it alone)
+    P.set_views_in_flight(1)
     lib.scoup_stage_timing(1)
     step()
+    P.set_views_in_flight(args.views_in_flight)
     stages = {}
     for sid, name in enumerate(STAGES):
         tot, cnt = C.c_double(), C.c_int64()
@@ -428,8 +435,10 @@ def main():
                         f"{w.width}x{w.height}, M={m}, K_code={sc.views.k_code}, Top-K={k}",
             "contributions_per_step": nc,
             "parallelism": "single GPU",
+            "views_in_flight": args.views_in_flight,
         },
         "stages": stages,
+        "stages_note": "per-stage kernel times from one extra step with one view in flight",
         "roofline": roofline,
         "cpu_baseline": cpu,
         "render_decode": render,

@@ -283,6 +283,21 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
 
+/* Views in flight in the uplift (scoup_uplift, scoup_uplift_accumulate,
+ * scoup_uplift_levels): up to k views of a view batch are projected, binned
+ * and composited at the same time, each with its own binning buffers, view i
+ * on lane i mod k; lane 0 runs on the call's stream, the others on streams
+ * the library creates once per device (default priority) and orders against
+ * the call's stream with events.  The sum of Eq. 5 does not depend on k; the
+ * deferred further-region weights of different views may reach the
+ * accumulator in another order (float rounding only).  k is clamped to
+ * [1, 4]; the default is 4.  The workspace sizes returned by the
+ * *_workspace_bytes functions cover 4 views in flight, so k may change
+ * between calls.  Process-wide setting, read at each call;
+ * scoup_views_in_flight returns the current value. */
+void scoup_set_views_in_flight(int32_t k);
+int32_t scoup_views_in_flight(void);
+
 /* ---------------------------------------------------------------------------
  * Several semantic levels in one pass (Sec. 4.1: SAM masks at three
  * granularities, each level run independently).  The blending weights e of

@@ -277,6 +277,15 @@ def topk(acc: torch.Tensor, k: int, stream=None):
     return idx, val
 
 
+def set_views_in_flight(k: int) -> None:
+    """Views the uplift projects, bins and composites at the same time (1..4)."""
+    L.load().scoup_set_views_in_flight(int(k))
+
+
+def views_in_flight() -> int:
+    return int(L.load().scoup_views_in_flight())
+
+
 def uplift(g: DeviceGaussians, views: DeviceViews, k: int, stream=None, workspace=None,
            pair_capacity: int = 0, view_batch: int = 0, acc: Optional[torch.Tensor] = None):
     """Algorithm 1: accumulate over all views, then Top-K (fused into the last

@@ -89,37 +89,45 @@ int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
   return mt;
 }
 
-// The uplift keeps two views in flight (binning of one overlapping the
-// compositing of the other) when a view batch holds two or more views: a
-// second set of per-view binning buffers follows the first layout.
+// The uplift keeps up to kLanes views in flight (binning of one overlapping
+// the compositing of another) when a view batch holds two or more views:
+// further sets of per-view binning buffers follow the first layout.
+constexpr int kLanes = 4;                     // workspace sized for this many; the setting below may use fewer
+int g_views_in_flight = kLanes;
 BinLayout uplift_layout(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
   return bin_layout(n, mt, cap, vb, vb * n_levels, true);
 }
 BinLayout uplift_lane2_layout(int64_t n, int mt, int64_t cap) { return bin_layout(n, mt, cap, 0, 0, true); }
+int uplift_lanes(int vb) { return std::max(1, std::min(g_views_in_flight, vb)); }
 size_t uplift_layout_total(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
   const size_t t = uplift_layout(n, mt, cap, vb, n_levels).total;
-  return vb >= 2 ? align256(t) + uplift_lane2_layout(n, mt, cap).total : t;
+  const int lanes = std::max(1, std::min(kLanes, vb));
+  return lanes > 1 ? align256(t) + (size_t)(lanes - 1) * align256(uplift_lane2_layout(n, mt, cap).total) : t;
 }
 
-// The library's second stream on the current device (default priority), and
-// events ordering it against the caller's stream; created on first use.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t ev[3] = {};
+// The library's further streams on the current device (default priority),
+// and events ordering them against the caller's stream; created on first use.
+struct SideStreams {
+  hipStream_t s[kLanes - 1] = {};
+  hipEvent_t start = nullptr, batch = nullptr;   // recorded on the caller's stream
+  hipEvent_t done[kLanes - 1] = {};              // recorded on the library streams
 };
 std::mutex g_side_mu;
-SideStream g_side[64];
-hipError_t side_stream(SideStream** out) {
+SideStreams g_side[64];
+hipError_t side_streams(SideStreams** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   std::lock_guard<std::mutex> lk(g_side_mu);
-  SideStream& ss = g_side[dev];
-  if (!ss.s) {
-    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) { ss.s = nullptr; return e; }
-    for (int k = 0; k < 3; ++k)
-      if ((e = hipEventCreateWithFlags(&ss.ev[k], hipEventDisableTiming)) != hipSuccess) return e;
+  SideStreams& ss = g_side[dev];
+  if (!ss.start) {
+    for (int k = 0; k < kLanes - 1; ++k) {
+      if ((e = hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&ss.done[k], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if ((e = hipEventCreateWithFlags(&ss.batch, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.start, hipEventDisableTiming)) != hipSuccess) return e;
   }
   *out = &ss;
   return hipSuccess;
@@ -277,6 +285,10 @@ int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches) {
 }
 
 
+void scoup_set_views_in_flight(int32_t k) { g_views_in_flight = std::max(1, std::min<int>(kLanes, k)); }
+
+int32_t scoup_views_in_flight(void) { return g_views_in_flight; }
+
 const char* scoup_last_error(void) { return g_err.c_str(); }
 
 const char* scoup_version(void) { return "libscoup 0.1 gfx950"; }
@@ -331,7 +343,7 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
                                            std::max(1, v->n_views)));
   const int mt = max_tiles_of(v);
   const BinLayout L = uplift_layout(g->n, mt, pair_capacity, vb, n_levels);
-  const int lanes = vb >= 2 ? 2 : 1;          // views in flight
+  const int lanes = uplift_lanes(vb);          // views in flight
   const size_t need = uplift_layout_total(g->n, mt, pair_capacity, vb, n_levels);
   if (ws_bytes < need) {
     g_required_pairs = pair_capacity;
@@ -340,28 +352,30 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   }
   HIP_TRY(ensure_lds_limits());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SideStream* side = nullptr;
-  if (lanes == 2) HIP_TRY(side_stream(&side));
+  SideStreams* side = nullptr;
+  if (lanes > 1) HIP_TRY(side_streams(&side));
   char* base = static_cast<char*>(ws);
   const BinLayout L2 = uplift_lane2_layout(g->n, mt, pair_capacity);
-  char* base2 = base + align256(L.total);
-  Status* status[2] = {reinterpret_cast<Status*>(base + L.status),
-                       lanes == 2 ? reinterpret_cast<Status*>(base2 + L2.status) : nullptr};
+  char* lane_base[kLanes] = {base};
+  for (int k = 1; k < lanes; ++k) lane_base[k] = base + align256(L.total) + (size_t)(k - 1) * align256(L2.total);
+  Status* status[kLanes] = {};
+  status[0] = reinterpret_cast<Status*>(base + L.status);
+  for (int k = 1; k < lanes; ++k) status[k] = reinterpret_cast<Status*>(lane_base[k] + L2.status);
   for (int k = 0; k < lanes; ++k) HIP_TRY(hipMemsetAsync(status[k], 0, sizeof(Status), s));
   const size_t acc_bytes = sizeof(float) * (size_t)g->n * (size_t)v->m_atoms;
   if (!accumulate && acc_bytes)
     for (int l = 0; l < n_levels; ++l) HIP_TRY(hipMemsetAsync(acc[l], 0, acc_bytes, s));
 
   // lane k: binning buffers, status and deferred entries of the views it handles; views
-  // alternate between the lanes, lane 0 on the caller's stream, lane 1 on the side stream
-  UpliftViewArgs a[2] = {};
+  // go round the lanes, lane 0 on the caller's stream, the others on the library's streams
+  UpliftViewArgs a[kLanes] = {};
   fill_bin(a[0].bin, g, base, L, pair_capacity, 3, kSortCap);
   a[0].extra = reinterpret_cast<float4*>(base + L.extra);
   a[0].extra_cap = L.extra_cap;
-  if (lanes == 2) {
-    fill_bin(a[1].bin, g, base2, L2, pair_capacity, 3, kSortCap);
-    a[1].extra = reinterpret_cast<float4*>(base2 + L2.extra);
-    a[1].extra_cap = L2.extra_cap;
+  for (int k = 1; k < lanes; ++k) {
+    fill_bin(a[k].bin, g, lane_base[k], L2, pair_capacity, 3, kSortCap);
+    a[k].extra = reinterpret_cast<float4*>(lane_base[k] + L2.extra);
+    a[k].extra_cap = L2.extra_cap;
   }
   unsigned int* off_all = a[0].bin.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
@@ -374,10 +388,11 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
       a[k].lv[l].k_code = lvs[l].k_code; a[k].lv[l].acc = acc[l];
     }
   }
-  hipStream_t strm[2] = {s, side ? side->s : s};
-  if (lanes == 2) {                            // lane 1 starts after the clears above
-    HIP_TRY(hipEventRecord(side->ev[0], s));
-    HIP_TRY(hipStreamWaitEvent(side->s, side->ev[0], 0));
+  hipStream_t strm[kLanes] = {s};
+  for (int k = 1; k < lanes; ++k) strm[k] = side->s[k - 1];
+  if (lanes > 1) {                            // the other lanes start after the clears above
+    HIP_TRY(hipEventRecord(side->start, s));
+    for (int k = 1; k < lanes; ++k) HIP_TRY(hipStreamWaitEvent(strm[k], side->start, 0));
   }
   const bool want_topk = k_top > 0;
   if (g->n > 0) {
@@ -402,9 +417,9 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         }
         HIP_TRY(launch_uplift_view(av, strm[j % lanes]));
       }
-      if (lanes == 2) {                        // the row build reads the records of both lanes
-        HIP_TRY(hipEventRecord(side->ev[1], side->s));
-        HIP_TRY(hipStreamWaitEvent(s, side->ev[1], 0));
+      for (int k = 1; k < lanes; ++k) {        // the row build reads the records of every lane
+        HIP_TRY(hipEventRecord(side->done[k - 1], strm[k]));
+        HIP_TRY(hipStreamWaitEvent(s, side->done[k - 1], 0));
       }
       const bool last = v0 + vb >= v->n_views;
       for (int l = 0; l < n_levels; ++l) {
@@ -421,9 +436,9 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         rb.entropy = (entropy && last) ? entropy[l] : nullptr;
         HIP_TRY(launch_rowbuild(rb, s));
       }
-      if (lanes == 2 && !last) {               // the next batch reuses the records and offsets
-        HIP_TRY(hipEventRecord(side->ev[2], s));
-        HIP_TRY(hipStreamWaitEvent(side->s, side->ev[2], 0));
+      if (lanes > 1 && !last) {                // the next batch reuses the records and offsets
+        HIP_TRY(hipEventRecord(side->batch, s));
+        for (int k = 1; k < lanes; ++k) HIP_TRY(hipStreamWaitEvent(strm[k], side->batch, 0));
       }
     }
     if (v->n_views == 0)
@@ -432,16 +447,19 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
         if (entropy && entropy[l]) HIP_TRY(launch_entropy(acc[l], g->n, v->m_atoms, entropy[l], s));
       }
   }
-  Status h{}, h2{};
+  Status hs[kLanes] = {};
   for (int k = 0; k < lanes; ++k) {
     if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status[k], s));
-    HIP_TRY(hipMemcpyAsync(k ? &h2 : &h, status[k], sizeof(Status), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hs[k], status[k], sizeof(Status), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   StageTimer::collect();
-  h.any_overflow |= h2.any_overflow;
-  h.max_pairs = std::max(h.max_pairs, h2.max_pairs);
-  h.data_error |= h2.data_error;
+  Status h = hs[0];
+  for (int k = 1; k < lanes; ++k) {
+    h.any_overflow |= hs[k].any_overflow;
+    h.max_pairs = std::max(h.max_pairs, hs[k].max_pairs);
+    h.data_error |= hs[k].data_error;
+  }
   if (h.any_overflow) {
     g_required_pairs = (int64_t)h.max_pairs;
     return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(pair_capacity) + " exceeded; need " +

@@ -319,3 +319,28 @@ def test_block_list_lengths_at_sort_class_edges(n):
     v = S.views_for([cam], [rm], idx, val, 16)
     sa, st, ref = _compare(g, v, 4, f"list{n}")
     assert ref.n_contrib >= 64 * min(n, 1800)
+
+
+@pytest.mark.parametrize("vif", [1, 2, 3])
+def test_views_in_flight_settings_agree(vif):
+    """Fewer views in flight than the default 4 (and a view batch that does
+    not divide by it): the same accumulator up to float rounding of the
+    deferred entries' order, and the oracle's parity."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    v = sg.make_views(77, sc.views.cameras, 300, 64, 4, hole_sites=1)
+    dg, dv = to_device(sc.gaussians, v)
+    try:
+        P.set_views_in_flight(vif)
+        assert P.views_in_flight() == vif
+        _, _, acc_k, nc_k = P.uplift(dg, dv, 4)
+        P.set_views_in_flight(4)
+        _, _, acc_4, nc_4 = P.uplift(dg, dv, 4)
+        torch.cuda.synchronize()
+    finally:
+        P.set_views_in_flight(4)
+    assert nc_k == nc_4
+    a, b = acc_k.cpu().numpy(), acc_4.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-5, atol=1e-7)
+    ref = OU.uplift_accumulate(sc.gaussians, v)
+    PT.check_acc(a, ref.acc, ref.amb)
