@@ -143,22 +143,42 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
   const int ct0 = cq * NCT;
   for (int k0 = 0; k0 < kpad; k0 += kc) {
     const int kcur = min(kc, kpad - k0);
-    // stage rows [p0, p0+128) x k [k0, k0+kcur) in 16-byte chunks, zero beyond M and P
+    // stage rows [p0, p0+128) x k [k0, k0+kcur) in 16-byte chunks, zero beyond M and P;
+    // with 16-byte aligned rows a thread issues all its chunk loads before their LDS stores
     const int chunks = kcur * F::ES / 16;
-    for (int c = tid; c < kDecBM * chunks; c += kDecThreads) {
-      const int r = c / chunks, q = c - r * chunks;
-      i32x4 v = {0, 0, 0, 0};
-      const long long p = p0 + r;
-      const int off = k0 * F::ES + q * 16;
-      if (p < P) {
-        const uint8_t* src = A + p * src_row + off;
-        if (off + 16 <= src_row && (src_row & 15) == 0) {
-          v = *reinterpret_cast<const i32x4*>(src);
-        } else {
-          for (int b = 0; b < 16 && off + b < src_row; ++b) reinterpret_cast<uint8_t*>(&v)[b] = src[b];
+    const int total = kDecBM * chunks;
+    if ((src_row & 15) == 0) {
+      constexpr int U = 8;
+      for (int c0 = tid; c0 < total; c0 += kDecThreads * U) {
+        i32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int c = c0 + u * kDecThreads;
+          const int r = c / chunks, q = c - r * chunks;
+          const int off = k0 * F::ES + q * 16;
+          v[u] = (i32x4){0, 0, 0, 0};
+          if (c < total && p0 + r < P && off + 16 <= src_row)
+            v[u] = *reinterpret_cast<const i32x4*>(A + (p0 + r) * src_row + off);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int c = c0 + u * kDecThreads;
+          const int r = c / chunks, q = c - r * chunks;
+          if (c < total) *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v[u];
         }
       }
-      *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
+    } else {
+      for (int c = tid; c < total; c += kDecThreads) {
+        const int r = c / chunks, q = c - r * chunks;
+        i32x4 v = {0, 0, 0, 0};
+        const long long p = p0 + r;
+        const int off = k0 * F::ES + q * 16;
+        if (p < P) {
+          const uint8_t* src = A + p * src_row + off;
+          for (int b = 0; b < 16 && off + b < src_row; ++b) reinterpret_cast<uint8_t*>(&v)[b] = src[b];
+        }
+        *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
+      }
     }
     __syncthreads();
     // codebook fragments for k-step ks are loaded one step ahead of their MFMAs
