@@ -4,10 +4,12 @@
 // per-tensor scales (v_mfma_scale_f32_32x32x64_f8f6f4, unit block scales).
 // Output float32 or bfloat16.
 //
-// Workgroup: 8 waves, a 128-pixel x D tile.  The 128 x M coefficient rows are
-// staged once in LDS; the codebook is pre-arranged in MFMA B-fragment order
-// (one 1 KB coalesced load per 32-column tile and k-step) and read from L2.
-// Wave w owns pixels [64 (w/4), +64) and columns [(w%4) D/4, +D/4).
+// Workgroup: 8 waves, one 128-pixel x D tile at a time (one workgroup per CU
+// walks the tiles).  The 128 x M coefficient rows are staged in LDS, each
+// thread issuing its 16-byte row loads together; the codebook is pre-arranged
+// in MFMA B-fragment order (one 1 KB coalesced load per 32-column tile and
+// k-step) and read from L2.  Wave w owns pixels [64 (w/4), +64) and columns
+// [(w%4) D/4, +D/4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,6 +54,7 @@ template <> struct Frag<SCOUP_FP8_E4M3> {
 
 constexpr int kDecBM = 128;
 constexpr int kDecThreads = 512;
+constexpr int kDecGrid = 256;                 // one workgroup per CU (registers allow one)
 
 // lane l of a 32x32 MFMA operand covers row/col (l % 32) and the k-slice
 // [(l / 32) * KS/2, +KS/2) of the k-step.
@@ -128,27 +131,24 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
                                                         int n_valid, int ldo, TOut* __restrict__ out,
                                                         float out_mul, const float* __restrict__ cb_scale) {
   using F = Mfma<T>;
+  using FT = typename Frag<T>::type;
   extern __shared__ uint8_t sA[];                     // kDecBM rows of kc elements (+16 B pad)
   const int row_bytes = kc * F::ES + 16;
-  const long long p0 = (long long)blockIdx.x * kDecBM;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int src_row = M * F::ES;
   const int rh = wave >> 2, cq = wave & 3;
-  f16v acc[2][NCT];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) acc[a][c] = (f16v){};
   const int nks = kpad / F::KS;
   const int ct0 = cq * NCT;
-  for (int k0 = 0; k0 < kpad; k0 += kc) {
-    const int kcur = min(kc, kpad - k0);
-    // stage rows [p0, p0+128) x k [k0, k0+kcur) in 16-byte chunks, zero beyond M and P;
-    // with 16-byte aligned rows a thread issues all its chunk loads before their LDS stores
+  const long long n_tiles = (P + kDecBM - 1) / kDecBM;
+  float mul = out_mul;
+  if (cb_scale) mul /= *cb_scale;
+  // workgroups walk tiles blockIdx.x, + gridDim.x, ...
+  constexpr int U = 8;                         // 16-byte row pieces a thread loads before storing them
+  // rows [p0, p0+128) x k [k0, k0+kcur) in 16-byte chunks, zero beyond M and P
+  auto stage_chunk = [&](long long p0, int k0, int kcur) {
     const int chunks = kcur * F::ES / 16;
     const int total = kDecBM * chunks;
     if ((src_row & 15) == 0) {
-      constexpr int U = 8;
       for (int c0 = tid; c0 < total; c0 += kDecThreads * U) {
         i32x4 v[U];
 #pragma unroll
@@ -180,61 +180,79 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
         *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
       }
     }
-    __syncthreads();
-    // codebook fragments for k-step ks are loaded one step ahead of their MFMAs
-    typename Frag<T>::type bcur[NCT], bnext[NCT];
-    const typename Frag<T>::type* Bf = reinterpret_cast<const typename Frag<T>::type*>(Bp);
+  };
+  // the MFMAs of k [k0, k0+kcur) from LDS for column tiles cb .. cb + NC - 1 of
+  // the wave (acc is f16v[2][NC]); codebook fragments one k-step ahead
+  auto mfma_cols = [&](int k0, int kcur, int cb, auto& acc) {
+    constexpr int NC = (int)(sizeof(acc[0]) / sizeof(f16v));
+    FT bcur[NC], bnext[NC];
+    const FT* Bf = reinterpret_cast<const FT*>(Bp);
 #pragma unroll
-    for (int c = 0; c < NCT; ++c) bcur[c] = Bf[((long long)(ct0 + c) * nks + k0 / F::KS) * 64 + lane];
+    for (int c = 0; c < NC; ++c) bcur[c] = Bf[((long long)(cb + c) * nks + k0 / F::KS) * 64 + lane];
     for (int kk = 0; kk < kcur; kk += F::KS) {
       const int ks = (k0 + kk) / F::KS;
       if (kk + F::KS < kcur) {
 #pragma unroll
-        for (int c = 0; c < NCT; ++c) bnext[c] = Bf[((long long)(ct0 + c) * nks + ks + 1) * 64 + lane];
+        for (int c = 0; c < NC; ++c) bnext[c] = Bf[((long long)(cb + c) * nks + ks + 1) * 64 + lane];
       }
       const int kb = (kk + (lane >> 5) * (F::KS / 2)) * F::ES;   // byte offset in the LDS row
-      const typename Frag<T>::type a0 =
-          *reinterpret_cast<const typename Frag<T>::type*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
-      const typename Frag<T>::type a1 =
-          *reinterpret_cast<const typename Frag<T>::type*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
+      const FT a0 = *reinterpret_cast<const FT*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
+      const FT a1 = *reinterpret_cast<const FT*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
       // operands swapped: the tile is F^T = C^T W^T, so each lane owns one pixel
       // and runs of four consecutive feature columns (vector stores below)
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) {
+      for (int c = 0; c < NC; ++c) {
         acc[0][c] = Frag<T>::mfma(bcur[c], a0, acc[0][c]);
         acc[1][c] = Frag<T>::mfma(bcur[c], a1, acc[1][c]);
       }
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) bcur[c] = bnext[c];
+      for (int c = 0; c < NC; ++c) bcur[c] = bnext[c];
     }
-    __syncthreads();
-  }
-  float mul = out_mul;
-  if (cb_scale) mul /= *cb_scale;
+  };
   // element (row 8(r/4) + 4(l/32) + r%4, col l%32) of each 32x32 tile of F^T:
-  // pixel p0 + rh*64 + a*32 + l%32, feature column (ct0+c)*32 + 8(r/4) + 4(l/32) + r%4
-  const bool vec = (ldo & 3) == 0;
+  // pixel p0 + rh*64 + a*32 + l%32, feature column (cb+c)*32 + 8(r/4) + 4(l/32) + r%4
+  auto epilogue = [&](long long p0, int cb, const auto& acc) {
+    constexpr int NC = (int)(sizeof(acc[0]) / sizeof(f16v));
+    const bool vec = (ldo & 3) == 0;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const long long p = p0 + rh * 64 + a * 32 + (lane & 31);
-    if (p >= P) continue;
-    TOut* orow = out + p * ldo;
+    for (int a = 0; a < 2; ++a) {
+      const long long p = p0 + rh * 64 + a * 32 + (lane & 31);
+      if (p >= P) continue;
+      TOut* orow = out + p * ldo;
 #pragma unroll
-    for (int c = 0; c < NCT; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int rg = 0; rg < 4; ++rg) {
-        const int d0 = (ct0 + c) * 32 + 8 * rg + 4 * (lane >> 5);
-        const float v0 = acc[a][c][4 * rg] * mul, v1 = acc[a][c][4 * rg + 1] * mul;
-        const float v2 = acc[a][c][4 * rg + 2] * mul, v3 = acc[a][c][4 * rg + 3] * mul;
-        if (vec && d0 + 3 < n_valid) {
-          store4(orow + d0, v0, v1, v2, v3);
-        } else {
-          if (d0 < n_valid) store_f(orow + d0, v0);
-          if (d0 + 1 < n_valid) store_f(orow + d0 + 1, v1);
-          if (d0 + 2 < n_valid) store_f(orow + d0 + 2, v2);
-          if (d0 + 3 < n_valid) store_f(orow + d0 + 3, v3);
+        for (int rg = 0; rg < 4; ++rg) {
+          const int d0 = (cb + c) * 32 + 8 * rg + 4 * (lane >> 5);
+          const float v0 = acc[a][c][4 * rg] * mul, v1 = acc[a][c][4 * rg + 1] * mul;
+          const float v2 = acc[a][c][4 * rg + 2] * mul, v3 = acc[a][c][4 * rg + 3] * mul;
+          if (vec && d0 + 3 < n_valid) {
+            store4(orow + d0, v0, v1, v2, v3);
+          } else {
+            if (d0 < n_valid) store_f(orow + d0, v0);
+            if (d0 + 1 < n_valid) store_f(orow + d0 + 1, v1);
+            if (d0 + 2 < n_valid) store_f(orow + d0 + 2, v2);
+            if (d0 + 3 < n_valid) store_f(orow + d0 + 3, v3);
+          }
         }
-      }
+    }
+  };
+
+  for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const long long p0 = tile * kDecBM;
+    f16v acc[2][NCT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) acc[a][c] = (f16v){};
+    for (int k0 = 0; k0 < kpad; k0 += kc) {
+      const int kcur = min(kc, kpad - k0);
+      stage_chunk(p0, k0, kcur);
+      __syncthreads();
+      mfma_cols(k0, kcur, ct0, acc);
+      __syncthreads();
+    }
+    epilogue(p0, ct0, acc);
   }
 }
 
@@ -323,7 +341,8 @@ hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void
   const int grid = (int)((total + 255) / 256);
   if (in_dtype == SCOUP_FP8_E4M3) {
     unsigned int* maxbits = reinterpret_cast<unsigned int*>(scale + 1);
-    hipMemsetAsync(maxbits, 0, sizeof(unsigned int), s);
+    const hipError_t e = hipMemsetAsync(maxbits, 0, sizeof(unsigned int), s);
+    if (e != hipSuccess) return e;
     const long long n = (long long)m * d;
     const int gb = (int)std::min<long long>(256, (n + 255) / 256);
     hipLaunchKernelGGL(k_absmax, dim3(gb), dim3(256), 0, s, C, n, maxbits);
@@ -342,8 +361,9 @@ hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage) {
   const size_t lds = decode_lds_bytes(a.m, a.in_dtype);
-  const int grid = (int)((a.P + kDecBM - 1) / kDecBM);
-  if (grid == 0) return hipSuccess;
+  const long long tiles = (a.P + kDecBM - 1) / kDecBM;
+  if (tiles == 0) return hipSuccess;
+  const int grid = (int)std::min<long long>(tiles, kDecGrid);   // workgroups walk the tiles
   StageTimer::begin(stage, s);
   hipError_t e;
   if (a.in_dtype == SCOUP_F32)
