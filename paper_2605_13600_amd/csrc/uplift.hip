@@ -501,8 +501,13 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   // each run of them, and the run's last lane adds its code once (fewer
   // LDS atomics, which would otherwise collide on the same row entries).
   auto add_chunk = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc) {
-    int g = 0;                                 // last Gaussian whose range starts at or before r
-    for (int t = 1; t < gn; ++t) g = r >= (unsigned int)__builtin_amdgcn_readlane((int)ob, t) ? t : g;
+    int g = 0;                                 // last Gaussian whose range starts at or before r:
+#pragma unroll                                 // binary search over the starts held by lanes 0..gn-1
+    for (int step = 8; step >= 1; step >>= 1) {
+      const int cand = g + step;
+      const unsigned int sc = (unsigned int)__shfl((int)ob, min(cand, 63), 64);
+      if (cand < gn && r >= sc) g = cand;
+    }
     const int reg = __float_as_int(rc.x);
     const bool valid = r < r1 && rc.y != 0.0f && reg >= 0 && reg < a.r_total;
     const int gk = valid ? g : -1;
