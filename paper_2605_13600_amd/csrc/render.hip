@@ -61,51 +61,85 @@ __global__ __launch_bounds__(64 * kRenderWaves) void k_render_coeff(
   float T = inside ? 1.0f : -1.0f;             // transmittance, negated once the pixel is finished
   unsigned int count = 0u;
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
-  for (int b0 = 0; b0 < L; b0 += kRenderBatch) {
-    if (__ballot(T > 0.0f) == 0ull) break;
-    const int nb = min(kRenderBatch, L - b0);
-    BlockSplat mine;
-    bool reach = false;                        // Gaussian `lane` reaches this wave's two pixel rows
-    if (lane < nb) {
-      const GSplat gs = splats[(unsigned int)keys[start + b0 + lane]];
-      mine.load(gs, tile_x0, tile_y0);
-      const BlockCull bc(gs, 3, W, H);
-      const int ry = tile_y0 + 2 * wave;
-      reach = ry < H && bc.live_rect(tile_x0, min(tile_x0 + 8, W) - 1, ry, min(ry + 2, H) - 1);
-    }
-    unsigned long long queue = __ballot(reach);
-    for (int t = lane; t < nb * K; t += 64) {
+  // The batch's ids arrive two batches ahead, its splats and code slots one
+  // batch ahead (registers), so no batch waits on a dependent load chain;
+  // indices past the list are clamped to its last entry (loads unconditional).
+  // Lane l holds Gaussian l & 15 of a batch; code slot t = l + 64 i of the
+  // batch is slot t % K of Gaussian t / K.
+  constexpr int TK = (kRenderBatch * kRenderKMax + 63) / 64;
+  const int kb = lane & (kRenderBatch - 1);
+  const int nslots = kRenderBatch * K;
+  auto key_at = [&](int i) { return (unsigned int)keys[start + min(i, L - 1)]; };
+  auto load_codes = [&](unsigned int keyv, int (&ci)[TK], float (&cv)[TK]) {
+#pragma unroll
+    for (int i = 0; i < TK; ++i) {
+      const int t = min(lane + 64 * i, nslots - 1);
       const int k = t / K, j = t - k * K;
-      const long long id = (long long)(unsigned int)keys[start + b0 + k];
-      ti[t] = topk_idx[id * K + j];
-      tv[t] = topk_val[id * K + j];
+      const unsigned int id = (unsigned int)__shfl((int)keyv, k, 64);
+      ci[i] = topk_idx[(long long)id * K + j];
+      cv[i] = topk_val[(long long)id * K + j];
     }
-    render_wave_lds_sync();
-    while (queue) {                            // only the batch Gaussians that reach these rows
-      const int k = __ffsll((long long)queue) - 1;
-      queue &= queue - 1ull;
-      const BlockSplat g = mine.bcast(k);
-      const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
-      const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
-      const float q = fmaf(u, u, v * v);
-      // branchless front-to-back step; a finished pixel keeps -T (its final transmittance, negated)
-      const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
-      const float testT = T * (1.0f - alpha);
-      const bool take = T > 0.0f && q <= g.qmax;
-      const bool keep = take && testT >= kTMin;
-      const float e = keep ? alpha * T : 0.0f;
-      T = take ? (keep ? testT : -T) : T;
-      if (keep) {
-        count += sub == 0 ? 1u : 0u;
-        for (int kk = sub; kk < K; kk += 4) {   // fire-and-forget LDS adds: no read-modify-write chain
-          const int jj = ti[k * K + kk];
-          if (jj >= 0 && jj < M) atomicAdd(&myrow[jj], e * tv[k * K + kk]);
-          else if (jj >= M) atomicOr(&st->data_error, 4u);
-        }
-      }
+  };
+  if (L > 0) {
+    unsigned int key_c = key_at(kb), key_n = key_at(kRenderBatch + kb);
+    GSplat sp_c = splats[key_c];
+    int ci_c[TK];
+    float cv_c[TK];
+    load_codes(key_c, ci_c, cv_c);
+    for (int b0 = 0; b0 < L; b0 += kRenderBatch) {
       if (__ballot(T > 0.0f) == 0ull) break;
+      const int nb = min(kRenderBatch, L - b0);
+      const GSplat sp_n = splats[key_n];
+      int ci_n[TK];
+      float cv_n[TK];
+      load_codes(key_n, ci_n, cv_n);
+      const unsigned int key_nn = key_at(b0 + 2 * kRenderBatch + kb);
+      BlockSplat mine;
+      bool reach = false;                      // Gaussian `lane` reaches this wave's two pixel rows
+      if (lane < nb) {
+        mine.load(sp_c, tile_x0, tile_y0);
+        const BlockCull bc(sp_c, 3, W, H);
+        const int ry = tile_y0 + 2 * wave;
+        reach = ry < H && bc.live_rect(tile_x0, min(tile_x0 + 8, W) - 1, ry, min(ry + 2, H) - 1);
+      }
+      unsigned long long queue = __ballot(reach);
+#pragma unroll
+      for (int i = 0; i < TK; ++i) {
+        const int t = lane + 64 * i;
+        if (t < nb * K) { ti[t] = ci_c[i]; tv[t] = cv_c[i]; }
+      }
+      render_wave_lds_sync();
+      while (queue) {                          // only the batch Gaussians that reach these rows
+        const int k = __ffsll((long long)queue) - 1;
+        queue &= queue - 1ull;
+        const BlockSplat g = mine.bcast(k);
+        const float dx = (pcx - g.hx) - g.fx, dy = (pcy - g.hy) - g.fy;
+        const float u = fmaf(g.l00, dx, g.l10 * dy), v = g.l11 * dy;
+        const float q = fmaf(u, u, v * v);
+        // branchless front-to-back step; a finished pixel keeps -T (its final transmittance, negated)
+        const float alpha = fminf(kAlphaMax, g.opacity * __builtin_amdgcn_exp2f(-q));
+        const float testT = T * (1.0f - alpha);
+        const bool take = T > 0.0f && q <= g.qmax;
+        const bool keep = take && testT >= kTMin;
+        const float e = keep ? alpha * T : 0.0f;
+        T = take ? (keep ? testT : -T) : T;
+        if (keep) {
+          count += sub == 0 ? 1u : 0u;
+          for (int kk = sub; kk < K; kk += 4) {   // fire-and-forget LDS adds: no read-modify-write chain
+            const int jj = ti[k * K + kk];
+            if (jj >= 0 && jj < M) atomicAdd(&myrow[jj], e * tv[k * K + kk]);
+            else if (jj >= M) atomicOr(&st->data_error, 4u);
+          }
+        }
+        if (__ballot(T > 0.0f) == 0ull) break;
+      }
+      render_wave_lds_sync();
+      key_c = key_n;
+      key_n = key_nn;
+      sp_c = sp_n;
+#pragma unroll
+      for (int i = 0; i < TK; ++i) { ci_c[i] = ci_n[i]; cv_c[i] = cv_n[i]; }
     }
-    render_wave_lds_sync();
   }
   if (inside && sub == 0 && t_final) t_final[(long long)py * W + px] = fabsf(T);
   unsigned long long total = count;
