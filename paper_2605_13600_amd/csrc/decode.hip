@@ -129,7 +129,8 @@ template <int T, int NCT, typename TOut>
 __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restrict__ A, long long P, int M,
                                                         int kpad, int kc, const uint8_t* __restrict__ Bp,
                                                         int n_valid, int ldo, TOut* __restrict__ out,
-                                                        float out_mul, const float* __restrict__ cb_scale) {
+                                                        float out_mul, const float* __restrict__ cb_scale,
+                                                        int staged_out) {
   using F = Mfma<T>;
   using FT = typename Frag<T>::type;
   extern __shared__ uint8_t sA[];                     // kDecBM rows of kc elements (+16 B pad)
@@ -252,7 +253,39 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
       mfma_cols(k0, kcur, ct0, acc);
       __syncthreads();
     }
-    epilogue(p0, ct0, acc);
+    if (staged_out) {
+      // 32 pixels at a time: the waves holding them write their rows into LDS
+      // (free after the k loop), then all threads store whole rows, 16 bytes a lane
+      constexpr int OES = (int)sizeof(TOut);
+      constexpr int OSTRIDE = 128 * NCT * OES + 16;
+      const int cpr = n_valid * OES / 16;
+#pragma unroll
+      for (int grp = 0; grp < 4; ++grp) {      // unrolled: acc[grp & 1] stays in registers
+        if (rh == (grp >> 1)) {
+          const int a = grp & 1;
+          TOut* row = reinterpret_cast<TOut*>(sA + (lane & 31) * OSTRIDE);
+#pragma unroll
+          for (int c = 0; c < NCT; ++c)
+#pragma unroll
+            for (int rg = 0; rg < 4; ++rg) {
+              const int d0 = (ct0 + c) * 32 + 8 * rg + 4 * (lane >> 5);
+              store4(row + d0, acc[a][c][4 * rg] * mul, acc[a][c][4 * rg + 1] * mul, acc[a][c][4 * rg + 2] * mul,
+                     acc[a][c][4 * rg + 3] * mul);
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < 32 * cpr; c += kDecThreads) {
+          const int r = c / cpr, q = c - r * cpr;
+          const long long p = p0 + grp * 32 + r;
+          if (p < P)
+            *reinterpret_cast<i32x4*>(reinterpret_cast<uint8_t*>(out) + p * (long long)ldo * OES + q * 16) =
+                *reinterpret_cast<const i32x4*>(sA + r * OSTRIDE + q * 16);
+        }
+        __syncthreads();
+      }
+    } else {
+      epilogue(p0, ct0, acc);
+    }
   }
 }
 
@@ -292,12 +325,25 @@ size_t decode_lds_bytes(int m, int in_dtype) {
   return (size_t)kDecBM * (decode_kchunk(m, in_dtype) * es + 16);
 }
 
+// Output rows staged through LDS and stored 16 bytes a lane (rows starting and
+// ending on 16-byte boundaries; the workgroup's LDS then covers 32 staged
+// rows): measured faster for float32 input (MFMA-bound, long k loop), slower
+// for BF16 / FP8 input, whose short k loop leaves the barriers exposed.
+template <int NCT, typename TOut>
+static bool decode_staged_out(const DecodeArgs& a) {
+  const int oes = (int)sizeof(TOut), ldo = a.ldo > 0 ? a.ldo : a.d;
+  return a.in_dtype == SCOUP_F32 && (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 &&
+         ((long long)ldo * oes) % 16 == 0 && (a.d * oes) % 16 == 0;
+}
+
 template <int T, int NCT, typename TOut>
 static void launch_dec(const DecodeArgs& a, hipStream_t s, size_t lds, int grid) {
+  const bool staged = decode_staged_out<NCT, TOut>(a);
+  if (staged) lds = std::max(lds, (size_t)32 * (128 * NCT * sizeof(TOut) + 16));
   hipLaunchKernelGGL((k_decode<T, NCT, TOut>), dim3(grid), dim3(kDecThreads), lds, s,
                      (const uint8_t*)a.coeff, a.P, a.m, a.kpad, decode_kchunk(a.m, a.in_dtype),
                      (const uint8_t*)a.codebook_prep, a.d, a.ldo > 0 ? a.ldo : a.d, (TOut*)a.out, a.out_mul,
-                     a.cb_scale);
+                     a.cb_scale, staged ? 1 : 0);
 }
 
 template <int T, typename TOut>
