@@ -224,22 +224,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     __syncthreads();
-    unsigned int contrib = 0u;                 // bit k: batch Gaussian k gave some pixel e > 0
+    int kend = 0;                              // E rows 0 .. kend-1 written in this batch
+    unsigned long long any_e = 0ull;           // pixels with some e > 0 in this batch
     if (!all_done) {
-      // one Gaussian of the batch, without branches: T < 0 marks a finished pixel
+      // One Gaussian of the batch, without branches.  T is -1 on a finished
+      // pixel (or one outside the image) and at least kTMin otherwise, so a
+      // Gaussian below the alpha threshold can run the same arithmetic with
+      // alpha = 0: testT = T exactly, E = 0, T kept; on a finished pixel
+      // testT < 0 fails the kTMin test and T stays -1.
       auto step = [&](int k, const float4& c0, const float4& c1, float cq) {
         // c0 = (hx, hy, fx, fy), c1 = (l00, l10, l11, opacity), cq = qmax
         const float dx = (pcx - c0.x) - c0.z, dy = (pcy - c0.y) - c0.w;
         const float u = fmaf(c1.x, dx, c1.y * dy), v = c1.z * dy;
         const float q = fmaf(u, u, v * v);
-        const float alpha = fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q));
+        const bool take = q <= cq;             // alpha >= 1/255
+        const float alpha = take ? fminf(kAlphaMax, c1.w * __builtin_amdgcn_exp2f(-q)) : 0.0f;
         const float testT = T * (1.0f - alpha);
-        const bool take = T > 0.0f && q <= cq;
-        const bool keep = take && testT >= kTMin;
-        E[k * kEStride + lane] = keep ? alpha * T : 0.0f;
-        T = take ? (keep ? testT : -1.0f) : T;
-        const unsigned long long kb = __ballot(keep);   // scalar bookkeeping
-        contrib |= (kb ? 1u : 0u) << k;
+        const bool keep = testT >= kTMin;
+        const float e = keep ? alpha * T : 0.0f;   // > 0 exactly when the Gaussian was taken and kept
+        E[k * kEStride + lane] = e;
+        T = keep ? testT : -1.0f;
+        const unsigned long long kb = __ballot(e > 0.0f);   // scalar bookkeeping
+        any_e |= kb;
         count += (unsigned long long)__popcll(kb);
       };
       // two register sets alternate so that each Gaussian's splat is read
@@ -251,18 +257,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const float4 b0v = s_bs[2 * k + 2], b1v = s_bs[2 * k + 3];
         const float bq = s_q[k + 1];
         step(k, a0, a1, aq);
+        kend = k + 1;
         if (k + 1 >= nb) break;
         a0 = s_bs[2 * k + 4]; a1 = s_bs[2 * k + 5]; aq = s_q[k + 2];
         step(k + 1, b0v, b1v, bq);
+        kend = k + 2;
         if (__ballot(T > 0.0f) == 0ull) break;
       }
     }
-    const unsigned long long contributed = contrib;
+    // bit k: E row k is this batch's (rows past kend hold an earlier batch's
+    // weights and count as zero); none when no pixel got a weight
+    const unsigned long long contributed = any_e ? (kend >= 32 ? 0xFFFFFFFFull : (1ull << kend) - 1ull) : 0ull;
     __syncthreads();
     if (two_class) {
       // lane group g sums Gaussian gk's row over the group's pixels of each
-      // class; rows of Gaussians without a contribution (stale ones included)
-      // are not read
+      // class; stale rows are not read
       float S0 = 0.0f, S1 = 0.0f;
       if (gk < nb && ((contributed >> gk) & 1ull)) {
         const float4* row4 = reinterpret_cast<const float4*>(E + gk * kEStride + gq0);
@@ -305,8 +314,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
       }
     } else {
-    // W = E M on the matrix cores; rows of Gaussians that did not contribute
-    // (stale E rows included) are replaced by zero below
+    // W = E M on the matrix cores; stale E rows are replaced by zero below
     f4v acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
     if (contributed) {
       const float* e0 = E + (lane & 15) * kEStride + 16 * kk;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     // lane holds W[g][col] for g = 4 kk + r (acc0) and 16 + 4 kk + r (acc1);
-    // rows of Gaussians without a contribution count as zero
+    // stale rows count as zero
     auto wval = [&](int i) {
       const int g = (i < 4 ? 0 : 16) + 4 * kk + (i & 3);
       const float a = i < 4 ? acc0[i & 3] : acc1[i & 3];
