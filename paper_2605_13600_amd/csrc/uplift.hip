@@ -43,7 +43,8 @@ namespace scoup {
 // with a per-region loop over E.
 // ---------------------------------------------------------------------------
 constexpr int kEStride = 68;                 // 64 pixels + 4: rows 16-byte aligned, b128 reads conflict-free
-constexpr int kCompositeBatch = 32;          // two 16-row MFMA tiles
+constexpr int kCompositeBatch = 32;          // Gaussians per batch: 16-row MFMA tiles
+constexpr int kCompositeWaves = 4;           // waves per SIMD the register budget allows
 constexpr int kCols = 16;                    // membership columns (one MFMA tile)
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -70,12 +71,13 @@ __device__ __forceinline__ void add_region_direct(const int* code_idx, const flo
   }
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_composite_blk(
+template <int B, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     const unsigned int* __restrict__ order,
     const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
-  constexpr int B = kCompositeBatch;
+  constexpr int NT = B / 16;                   // 16-Gaussian MFMA tiles per batch
   __shared__ __align__(16) float E[B * kEStride];
   __shared__ float4 s_bs[2 * (B + 2)];         // the batch's splats, block-relative: (hx, hy, fx, fy),
   __shared__ float s_q[B + 2];                 //   (l00, l10, l11, opacity) and qmax; two spare slots
@@ -315,34 +317,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     } else {
     // W = E M on the matrix cores; stale E rows are replaced by zero below
-    f4v acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+    f4v acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
     if (contributed) {
       const float* e0 = E + (lane & 15) * kEStride + 16 * kk;
-      const float* e1 = e0 + 16 * kEStride;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 x0 = *reinterpret_cast<const float4*>(e0 + 4 * q);
-        const float4 x1 = *reinterpret_cast<const float4*>(e1 + 4 * q);
-        const float xa[4] = {x0.x, x0.y, x0.z, x0.w}, xb[4] = {x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const float bv = (float)((mbits >> (4 * q + m)) & 1u);
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[m], bv, acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(xb[m], bv, acc1, 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+          const float4 x = *reinterpret_cast<const float4*>(e0 + 16 * t * kEStride + 4 * q);
+          const float xa[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const float bv = (float)((mbits >> (4 * q + m)) & 1u);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[m], bv, acc[t], 0, 0, 0);
+          }
         }
       }
     }
-    // lane holds W[g][col] for g = 4 kk + r (acc0) and 16 + 4 kk + r (acc1);
-    // stale rows count as zero
+    // lane holds W[g][col] for g = 16 t + 4 kk + r in acc[t][r]; stale rows count as zero
     auto wval = [&](int i) {
-      const int g = (i < 4 ? 0 : 16) + 4 * kk + (i & 3);
-      const float a = i < 4 ? acc0[i & 3] : acc1[i & 3];
+      const int g = 16 * (i >> 2) + 4 * kk + (i & 3);
+      const float a = acc[i >> 2][i & 3];
       return ((contributed >> g) & 1ull) ? a : 0.0f;
     };
     if (rec_col) {                             // every pair's record slots, zero weight included
       const float rg = __int_as_float(col_greg);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < NT; ++t) {
         const uint4 p4 = *reinterpret_cast<const uint4*>(&s_pidx[16 * t + 4 * kk]);
         const unsigned int pp[4] = {p4.x, p4.y, p4.z, p4.w};
 #pragma unroll
@@ -355,8 +358,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
       if (ext_col) {
         const unsigned long long row0 = ebase + (unsigned long long)b0 * n_ext + (unsigned long long)(col - 2 * n_levels);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int g = (i < 4 ? 0 : 16) + 4 * kk + (i & 3);
+        for (int i = 0; i < 4 * NT; ++i) {
+          const int g = 16 * (i >> 2) + 4 * kk + (i & 3);
           if (g < nb) {
             const unsigned long long slot = row0 + (unsigned long long)g * n_ext;
             const float w = wval(i);
@@ -378,9 +381,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             dF = args.lv[l].dense_F; dd = args.lv[l].dense_d; ac = args.lv[l].acc; zs = args.lv[l].zsum;
           }
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 4 * NT; ++i)
           if ((ovf >> i) & 1u)
-            add_region_direct(ci, cv, kc, dF, dd, ac, zs, s_gid[(i < 4 ? 0 : 16) + 4 * kk + (i & 3)], col_greg,
+            add_region_direct(ci, cv, kc, dF, dd, ac, zs, s_gid[16 * (i >> 2) + 4 * kk + (i & 3)], col_greg,
                               wval(i), m_atoms, st);
       }
     }
@@ -732,7 +735,7 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL(k_composite_blk, dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
+  hipLaunchKernelGGL((k_composite_blk<kCompositeBatch, kCompositeWaves>), dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
                      b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
   StageTimer::end(kStComposite, s);
