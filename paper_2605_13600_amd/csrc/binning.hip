@@ -268,11 +268,12 @@ __global__ __launch_bounds__(256) void k_scan_down(unsigned int* __restrict__ da
 // ---------------------------------------------------------------------------
 // Blocks the Gaussian cannot reach get the tile id n_tiles, which sorts after
 // every list and belongs to none.
-__global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats, long long n, int tiles_x,
+__global__ __launch_bounds__(256) void k_emit(GSplat* splats, long long n, int tiles_x,
                                               int n_tiles, int tile_shift, int W, int H,
                                               const unsigned int* __restrict__ off,
                                               unsigned int* __restrict__ tile_ids,
-                                              unsigned long long* __restrict__ keys, const Status* st) {
+                                              unsigned long long* __restrict__ keys, int keep_off,
+                                              const Status* st) {
   if (st->view_overflow) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(256) void k_emit(const GSplat* __restrict__ splats,
       tile_ids[p] = live ? (unsigned int)(ty * tiles_x + tx) : (unsigned int)n_tiles;
       keys[p] = key;
     }
+  if (keep_off) splats[i].depth_bits = off[i];   // the depth is in the keys now
 }
 
 // Every pair's uplift record slots start as (no region, 0): coalesced over
@@ -370,11 +372,12 @@ __global__ __launch_bounds__(256) void k_bin_colscan(unsigned int* __restrict__ 
   tile_len[t] = run;
 }
 
-__global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __restrict__ splats, long long n,
+__global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, long long n,
                                                              int tiles_x, int n_tiles, int tile_shift, int W, int H,
                                                              long long per_wg, const unsigned int* __restrict__ hist,
                                                              const unsigned int* __restrict__ tile_start,
                                                              unsigned long long* __restrict__ keys,
+                                                             const unsigned int* __restrict__ pair_off,
                                                              const Status* st) {
   extern __shared__ unsigned int h[];         // tickets: ceil(n_tiles / 2) words, then (images
   if (st->view_overflow) return;               // up to kCountPlaceLdsTiles blocks) start + base
@@ -404,6 +407,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(const GSplat* __res
         const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
         keys[(staged ? sb[t] : tile_start[t] + base[t]) + ticket] = key;
       }
+    if (pair_off) splats[i].depth_bits = pair_off[i];   // the depth is in the keys now
   }
 }
 
@@ -999,7 +1003,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     StageTimer::begin(kStEmit, s);
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.n_tiles, a.tile_shift,
                        a.cam.width, a.cam.height, (const unsigned int*)a.offsets, a.tile_ids[0], a.keys[0],
-                       a.status);
+                       a.n_cull_records > 0 ? 1 : 0, a.status);
     StageTimer::end(kStEmit, s);
   }
   StageTimer::begin(kStSortBig, s);
@@ -1019,7 +1023,8 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds_place, s,
                        a.splats, a.n, a.tiles_x, a.n_tiles,
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, (const unsigned int*)a.bin_hist,
-                       (const unsigned int*)a.tile_start, a.keys[0], a.status);
+                       (const unsigned int*)a.tile_start, a.keys[0],
+                       a.n_cull_records > 0 ? (const unsigned int*)a.offsets : nullptr, a.status);
     a.sorted = 0;
     sort_lists(a, s, true);
     StageTimer::end(kStSortBig, s);

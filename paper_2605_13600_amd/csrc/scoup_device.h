@@ -28,7 +28,8 @@ struct __align__(16) GSplat {
   float fx, fy;
   float l00, l10, l11, opacity;
   int16_t bx0, bx1, by0, by1;
-  uint32_t depth_bits;   // float32 view depth (positive, so bits order like values)
+  uint32_t depth_bits;   // float32 view depth (positive, so bits order like values); once an
+                         // uplift view's pairs are placed, the Gaussian's first pair index instead
   uint32_t live;         // reachable blocks among the first 32 of the box (see pair_live)
 };
 static_assert(sizeof(GSplat) == 48, "GSplat layout");

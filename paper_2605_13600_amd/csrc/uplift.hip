@@ -75,7 +75,7 @@ template <int B, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     const unsigned int* __restrict__ order,
-    const unsigned long long* __restrict__ keys, const unsigned int* __restrict__ off, int tiles_x, int W,
+    const unsigned long long* __restrict__ keys, int tiles_x, int W,
     int H, int n_levels, int m_atoms, UpliftViewArgs args, Status* st) {
   constexpr int NT = B / 16;                   // 16-Gaussian MFMA tiles per batch
   __shared__ __align__(16) float E[B * kEStride];
@@ -202,13 +202,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   unsigned long long key_cur = keys[start + min(gk, L - 1)];
   unsigned long long key_next = keys[start + min(B + gk, L - 1)];
   GSplat sp_cur = splats[(unsigned int)key_cur];
-  unsigned int off_cur = off[(unsigned int)key_cur];   // the Gaussian's first pair (record) index
+  unsigned int off_cur = sp_cur.depth_bits;   // the Gaussian's first pair (record) index (binning put it there)
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(T > 0.0f) == 0ull;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
     const GSplat sp_next = splats[(unsigned int)key_next];
-    const unsigned int off_next = off[(unsigned int)key_next];
+    const unsigned int off_next = sp_next.depth_bits;
     const unsigned long long key_after = keys[start + min(j + 2 * B, L - 1)];
     unsigned int my_id = 0;
     if (j < L) {
@@ -736,7 +736,7 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
   hipLaunchKernelGGL((k_composite_blk<kCompositeBatch, kCompositeWaves>), dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
-                     b.tile_order, b.keys[b.sorted], b.offsets, b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
+                     b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
                      a, b.status);
   StageTimer::end(kStComposite, s);
   if (a.extra_cap > 0) {
