@@ -302,7 +302,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         S0 += __shfl_xor(S0, o, 64);
         S1 += __shfl_xor(S1, o, 64);
       }
-      if (lane < nb) {                         // every pair's record slots, zero weight included
+      // the pair's record slots; binning cleared every pair's slots to (no
+      // region, 0), which readers skip like any zero weight, so a pair whose
+      // weights are both zero is not written
+      if (lane < nb) {
         const unsigned int p = s_pidx[lane];
 #pragma unroll
         for (int l = 0; l < kMaxLevels; ++l) {
@@ -310,9 +313,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
           const int c0 = (key0 >> (2 * l)) & 3, c1 = (key1 >> (2 * l)) & 3;
           const float w0 = (c0 == 0 ? S0 : 0.0f) + (c1 == 0 ? S1 : 0.0f);
           const float w1 = (c0 == 1 ? S0 : 0.0f) + (c1 == 1 ? S1 : 0.0f);
-          float2* rec = args.lv[l].records;
-          rec[2ull * p] = make_float2(__int_as_float(rg0[l]), w0);
-          rec[2ull * p + 1] = make_float2(__int_as_float(rg1[l]), w1);
+          if (w0 != 0.0f || w1 != 0.0f) {
+            float2* rec = args.lv[l].records;
+            rec[2ull * p] = make_float2(__int_as_float(rg0[l]), w0);
+            rec[2ull * p + 1] = make_float2(__int_as_float(rg1[l]), w1);
+          }
         }
       }
     } else {
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       const float a = acc[i >> 2][i & 3];
       return ((contributed >> g) & 1ull) ? a : 0.0f;
     };
-    if (rec_col) {                             // every pair's record slots, zero weight included
+    if (rec_col) {                             // the pairs' record slots of nonzero weight (as above)
       const float rg = __int_as_float(col_greg);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -350,7 +355,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const unsigned int pp[4] = {p4.x, p4.y, p4.z, p4.w};
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (16 * t + 4 * kk + r < nb) rec_out[2ull * pp[r] + (col & 1)] = make_float2(rg, wval(4 * t + r));
+          if (16 * t + 4 * kk + r < nb) {
+            const float w = wval(4 * t + r);
+            if (w != 0.0f) rec_out[2ull * pp[r] + (col & 1)] = make_float2(rg, w);
+          }
       }
     }
     if (n_ext > 0) {                           // further-region columns: this batch's entry slots
