@@ -205,6 +205,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   unsigned int off_cur = sp_cur.depth_bits;   // the Gaussian's first pair (record) index (binning put it there)
   for (int b0 = 0; b0 < L; b0 += B) {
     const bool all_done = __ballot(T > 0.0f) == 0ull;
+    // every pixel finished: the remaining pairs keep their cleared records;
+    // only deferred-entry slots (reserved for the whole list) still need zeros
+    if (all_done && n_ext == 0) break;
     const int j = b0 + gk;
     const int nb = min(B, L - b0);
     const GSplat sp_next = splats[(unsigned int)key_next];
