@@ -59,6 +59,19 @@ def test_anisotropic_multi_tile():
     _compare(g, v, 8, "aniso")
 
 
+def test_large_image_radix_binning():
+    """1920x1664 views (49,920 8x8 blocks, above the counting pass's 49,152):
+    pairs are emitted Gaussian-major and radix-sorted by block, and the
+    emission also leaves each Gaussian's first pair index in its splat for the
+    compositing."""
+    require_gpu()
+    g = sg.make_gaussians(91, 4000, (5.0, 5.0, 2.0), -4.0, 0.3, False, "beta")
+    cams = sg.orbit_cameras(92, 2, 12.0, 1.0, 4.0, 1.0, 0.5, 1920, 1664, 60.0)
+    v = sg.make_views(93, cams, 40, 64, 4)
+    sa, st, ref = _compare(g, v, 4, "radix")
+    assert ref.n_contrib > 500_000
+
+
 def test_dense_tile_sorted_in_global_memory():
     """A tile holding more splats than the LDS sort capacity takes the global sort."""
     require_gpu()
