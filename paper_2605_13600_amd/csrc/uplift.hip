@@ -514,28 +514,33 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     if (v >= a.n_views || lane > gn) return 0u;
     return 2u * min(a.offsets[(long long)v * (a.n + 1) + i0 + lane], cap);
   };
-  auto load_rec = [&](int v, unsigned int r, unsigned int r1) -> float2 {
-    return (v < a.n_views && r < r1) ? a.records[(long long)v * 2 * a.capacity + r] : make_float2(0.0f, 0.0f);
+  // record r of view v; past the view's range (or the views) the load still
+  // goes to a record of the batch, so it is issued unconditionally, and the
+  // value is dropped by the range test
+  const unsigned int rec_last = 2u * cap - 1u;
+  auto load_rec = [&](int v, unsigned int r) -> float2 {
+    return a.records[(long long)max(0, min(v, a.n_views - 1)) * 2 * a.capacity + min(r, rec_last)];
   };
-  // records of one 64-record chunk (record r of lane) into the rows.  Equal
-  // (Gaussian, region) records sit two lanes apart (the same slot of
-  // consecutive pairs): a segmented sum along lanes of equal parity folds
-  // each run of them, and the run's last lane adds its code once (fewer
-  // LDS atomics, which would otherwise collide on the same row entries).
-  auto add_chunk = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc) {
-    int g = 0;                                 // last Gaussian whose range starts at or before r:
+  // Records of one 64-record chunk (record r of lane) folded per (Gaussian,
+  // region): equal (Gaussian, region) records sit two lanes apart (the same
+  // slot of consecutive pairs), so a segmented sum along lanes of equal
+  // parity folds each run of them, and the run's last lane adds its code once
+  // (fewer LDS atomics, which would otherwise collide on the same row
+  // entries).  Returns whether this lane adds, with its row, region and weight.
+  auto fold = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc, int& g, int& reg, float& w) -> bool {
+    g = 0;                                     // last Gaussian whose range starts at or before r:
 #pragma unroll                                 // binary search over the starts held by lanes 0..gn-1
     for (int step = 8; step >= 1; step >>= 1) {
       const int cand = g + step;
       const unsigned int sc = (unsigned int)__shfl((int)ob, min(cand, 63), 64);
       if (cand < gn && r >= sc) g = cand;
     }
-    const int reg = __float_as_int(rc.x);
+    reg = __float_as_int(rc.x);
     const bool valid = r < r1 && rc.y != 0.0f && reg >= 0 && reg < a.r_total;
     const int gk = valid ? g : -1;
     const int pg = __shfl_up(gk, 2, 64), pr = __shfl_up(reg, 2, 64);
     bool head = !valid || lane < 2 || pg != gk || pr != reg;
-    float w = valid ? rc.y : 0.0f;
+    w = valid ? rc.y : 0.0f;
 #pragma unroll
     for (int d = 2; d < 64; d <<= 1) {
       const float wu = __shfl_up(w, d, 64);
@@ -543,7 +548,49 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
       if (lane >= d && !head) { w += wu; head = hu != 0; }
     }
     const int ng = __shfl_down(gk, 2, 64), nr = __shfl_down(reg, 2, 64);
-    if (!valid || (lane < 62 && ng == gk && nr == reg)) return;
+    return valid && !(lane < 62 && ng == gk && nr == reg);
+  };
+  auto add_code = [&](float* row, float w, int j, float c) {
+    if (j >= M) atomicOr(&a.status->data_error, 2u);
+    else if (j >= 0) atomicAdd(&row[j], w * c);
+  };
+  // Codes of up to 8 slots in 16-byte rows: a chunk's code loads are issued
+  // (unconditionally, an inactive lane reading region 0) before the previous
+  // chunk's adds, which use codes loaded one chunk earlier.
+  const bool piped = a.k_code <= 8 && a.r_total > 0 && (a.k_code & 3) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(a.code_idx) | reinterpret_cast<uintptr_t>(a.code_val)) & 15) == 0;
+  bool p_act = false;
+  int p_g = 0;
+  float p_w = 0.0f;
+  int4 p_j0 = make_int4(-1, -1, -1, -1), p_j1 = p_j0;
+  float4 p_c0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), p_c1 = p_c0;
+  auto add_pending = [&]() {
+    if (!p_act) return;
+    float* row = rows + p_g * stride;
+    add_code(row, p_w, p_j0.x, p_c0.x); add_code(row, p_w, p_j0.y, p_c0.y);
+    add_code(row, p_w, p_j0.z, p_c0.z); add_code(row, p_w, p_j0.w, p_c0.w);
+    if (a.k_code > 4) {
+      add_code(row, p_w, p_j1.x, p_c1.x); add_code(row, p_w, p_j1.y, p_c1.y);
+      add_code(row, p_w, p_j1.z, p_c1.z); add_code(row, p_w, p_j1.w, p_c1.w);
+    }
+  };
+  auto add_chunk = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc) {
+    int g, reg;
+    float w;
+    const bool act = fold(ob, r, r1, rc, g, reg, w);
+    if (piped) {
+      const long long gr = (long long)(act ? reg : 0) * a.k_code;
+      const int4 j0 = *reinterpret_cast<const int4*>(a.code_idx + gr);
+      const float4 c0 = *reinterpret_cast<const float4*>(a.code_val + gr);
+      const long long g1 = a.k_code > 4 ? gr + 4 : gr;
+      const int4 j1 = *reinterpret_cast<const int4*>(a.code_idx + g1);
+      const float4 c1 = *reinterpret_cast<const float4*>(a.code_val + g1);
+      add_pending();
+      p_act = act; p_g = g; p_w = w;
+      p_j0 = j0; p_j1 = j1; p_c0 = c0; p_c1 = c1;
+      return;
+    }
+    if (!act) return;
     float* row = rows + g * stride;
     const long long gr = (long long)reg * a.k_code;
     for (int c = 0; c < a.k_code; c += 4) {   // four slots' loads before their adds
@@ -562,10 +609,7 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (jj[u] >= M) atomicOr(&a.status->data_error, 2u);
-        else if (jj[u] >= 0) atomicAdd(&row[jj[u]], w * cv[u]);
-      }
+      for (int u = 0; u < 4; ++u) add_code(row, w, jj[u], cv[u]);
     }
   };
   // wave w walks views w, w+4, ...; the next view's offsets are loaded two
@@ -574,21 +618,22 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   unsigned int ob_c = load_ob(v), ob_n = load_ob(v + 4);
   unsigned int r0_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, 0);
   unsigned int r1_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, gn);
-  float2 rc_c = load_rec(v, r0_c + (unsigned int)lane, r1_c);
+  float2 rc_c = load_rec(v, r0_c + (unsigned int)lane);
   for (; v < a.n_views; v += 4) {
     const unsigned int ob_nn = load_ob(v + 8);
     const unsigned int r0_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, 0);
     const unsigned int r1_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, gn);
-    const float2 rc_n = load_rec(v + 4, r0_n + (unsigned int)lane, r1_n);
+    const float2 rc_n = load_rec(v + 4, r0_n + (unsigned int)lane);
     add_chunk(ob_c, r0_c + (unsigned int)lane, r1_c, rc_c);
     for (unsigned int base = r0_c + 64u; base < r1_c; base += 64u) {
       const unsigned int r = base + (unsigned int)lane;
-      add_chunk(ob_c, r, r1_c, load_rec(v, r, r1_c));
+      add_chunk(ob_c, r, r1_c, load_rec(v, r));
     }
     ob_c = ob_n; ob_n = ob_nn;
     r0_c = r0_n; r1_c = r1_n;
     rc_c = rc_n;
   }
+  add_pending();
   __syncthreads();
   for (int j = tid; j < gn * M; j += 256) acc[j] = rows[(j / M) * stride + (j % M)];
   if (a.k_top > 0) {
