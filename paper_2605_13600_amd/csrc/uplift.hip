@@ -541,11 +541,12 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     const int pg = __shfl_up(gk, 2, 64), pr = __shfl_up(reg, 2, 64);
     bool head = !valid || lane < 2 || pg != gk || pr != reg;
     w = valid ? rc.y : 0.0f;
+    // one shuffle per step: a weight is positive (records hold sums of e > 0)
+    // or, on an invalid lane, zero, so the run-head flag rides in the sign bit
 #pragma unroll
     for (int d = 2; d < 64; d <<= 1) {
-      const float wu = __shfl_up(w, d, 64);
-      const int hu = __shfl_up((int)head, d, 64);
-      if (lane >= d && !head) { w += wu; head = hu != 0; }
+      const float u = __shfl_up(head ? -w : w, d, 64);
+      if (lane >= d && !head) { w += fabsf(u); head = __builtin_signbit(u) != 0; }
     }
     const int ng = __shfl_down(gk, 2, 64), nr = __shfl_down(reg, 2, 64);
     return valid && !(lane < 62 && ng == gk && nr == reg);
