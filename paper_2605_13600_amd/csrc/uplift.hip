@@ -527,14 +527,18 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   // parity folds each run of them, and the run's last lane adds its code once
   // (fewer LDS atomics, which would otherwise collide on the same row
   // entries).  Returns whether this lane adds, with its row, region and weight.
-  auto fold = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc, int& g, int& reg, float& w) -> bool {
-    g = 0;                                     // last Gaussian whose range starts at or before r:
-#pragma unroll                                 // binary search over the starts held by lanes 0..gn-1
-    for (int step = 8; step >= 1; step >>= 1) {
-      const int cand = g + step;
-      const unsigned int sc = (unsigned int)__shfl((int)ob, min(cand, 63), 64);
-      if (cand < gn && r >= sc) g = cand;
-    }
+  // the view's record starts of Gaussians 1..G-1 as wave-uniform values (past
+  // the group: never reached), so a record's Gaussian is a count of compares
+  unsigned int sk[16];
+  auto set_starts = [&](unsigned int ob) {
+#pragma unroll
+    for (int k = 1; k < 16; ++k)
+      sk[k] = k < gn ? (unsigned int)__builtin_amdgcn_readlane((int)ob, k) : 0xFFFFFFFFu;
+  };
+  auto fold = [&](unsigned int r, unsigned int r1, float2 rc, int& g, int& reg, float& w) -> bool {
+    g = 0;                                     // last Gaussian whose range starts at or before r
+#pragma unroll
+    for (int k = 1; k < 16; ++k) g += r >= sk[k] ? 1 : 0;
     reg = __float_as_int(rc.x);
     const bool valid = r < r1 && rc.y != 0.0f && reg >= 0 && reg < a.r_total;
     const int gk = valid ? g : -1;
@@ -575,10 +579,10 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
       add_code(row, p_w, p_j1.z, p_c1.z); add_code(row, p_w, p_j1.w, p_c1.w);
     }
   };
-  auto add_chunk = [&](unsigned int ob, unsigned int r, unsigned int r1, float2 rc) {
+  auto add_chunk = [&](unsigned int r, unsigned int r1, float2 rc) {
     int g, reg;
     float w;
-    const bool act = fold(ob, r, r1, rc, g, reg, w);
+    const bool act = fold(r, r1, rc, g, reg, w);
     if (piped) {
       const long long gr = (long long)(act ? reg : 0) * a.k_code;
       const int4 j0 = *reinterpret_cast<const int4*>(a.code_idx + gr);
@@ -625,10 +629,11 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     const unsigned int r0_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, 0);
     const unsigned int r1_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, gn);
     const float2 rc_n = load_rec(v + 4, r0_n + (unsigned int)lane);
-    add_chunk(ob_c, r0_c + (unsigned int)lane, r1_c, rc_c);
+    set_starts(ob_c);
+    add_chunk(r0_c + (unsigned int)lane, r1_c, rc_c);
     for (unsigned int base = r0_c + 64u; base < r1_c; base += 64u) {
       const unsigned int r = base + (unsigned int)lane;
-      add_chunk(ob_c, r, r1_c, load_rec(v, r));
+      add_chunk(r, r1_c, load_rec(v, r));
     }
     ob_c = ob_n; ob_n = ob_nn;
     r0_c = r0_n; r1_c = r1_n;
