@@ -546,9 +546,11 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     bool head = !valid || lane < 2 || pg != gk || pr != reg;
     w = valid ? rc.y : 0.0f;
     // one shuffle per step: a weight is positive (records hold sums of e > 0)
-    // or, on an invalid lane, zero, so the run-head flag rides in the sign bit
+    // or, on an invalid lane, zero, so the run-head flag rides in the sign bit;
+    // the steps stop once every lane's sum reaches back to its run's head
 #pragma unroll
     for (int d = 2; d < 64; d <<= 1) {
+      if (__ballot(!head) == 0ull) break;
       const float u = __shfl_up(head ? -w : w, d, 64);
       if (lane >= d && !head) { w += fabsf(u); head = __builtin_signbit(u) != 0; }
     }
