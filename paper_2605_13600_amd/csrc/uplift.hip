@@ -544,6 +544,9 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     const int gk = valid ? g : -1;
     const int pg = __shfl_up(gk, 2, 64), pr = __shfl_up(reg, 2, 64);
     bool head = !valid || lane < 2 || pg != gk || pr != reg;
+    // the lane ends its run when the record two lanes on starts a run (or is
+    // past the chunk)
+    const bool next_head = __shfl_down((int)head, 2, 64) != 0;
     w = valid ? rc.y : 0.0f;
     // one shuffle per step: a weight is positive (records hold sums of e > 0)
     // or, on an invalid lane, zero, so the run-head flag rides in the sign bit;
@@ -554,8 +557,7 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
       const float u = __shfl_up(head ? -w : w, d, 64);
       if (lane >= d && !head) { w += fabsf(u); head = __builtin_signbit(u) != 0; }
     }
-    const int ng = __shfl_down(gk, 2, 64), nr = __shfl_down(reg, 2, 64);
-    return valid && !(lane < 62 && ng == gk && nr == reg);
+    return valid && (lane >= 62 || next_head);
   };
   auto add_code = [&](float* row, float w, int j, float c) {
     if (j >= M) atomicOr(&a.status->data_error, 2u);
