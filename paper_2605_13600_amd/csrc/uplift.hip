@@ -779,19 +779,34 @@ __global__ void k_add_u64(unsigned long long* dst, const Status* st) { *dst += s
 // ---------------------------------------------------------------------------
 // The deferred further-region weights of one view: w times the region's code
 // (or feature, for the dense uplift) added to the Gaussian's accumulator row.
-__global__ __launch_bounds__(256) void k_apply_extra(UpliftViewArgs a, int m_atoms, Status* st) {
+// One thread per (entry, code slot) -- or (entry, feature column), plus one
+// for Z, in the dense uplift -- so that each thread makes one atomic add.
+__global__ __launch_bounds__(256) void k_apply_extra(UpliftViewArgs a, int m_atoms, int width, Status* st) {
   if (st->view_overflow) return;
-  const unsigned long long n = min(st->n_extra, (unsigned long long)a.extra_cap);
+  const unsigned long long n = min(st->n_extra, (unsigned long long)a.extra_cap) * (unsigned long long)width;
   for (unsigned long long t = blockIdx.x * 256ull + threadIdx.x; t < n; t += gridDim.x * 256ull) {
-    const float4 r = a.extra[t];
+    const unsigned long long e = t / (unsigned int)width;
+    const int c = (int)(t - e * (unsigned int)width);
+    const float4 r = a.extra[e];
     if (!(r.w > 0.0f)) continue;             // reserved slot of a Gaussian without weight there
     const int l = __float_as_int(r.y);
+    const unsigned int id = __float_as_uint(r.x);
+    const long long greg = __float_as_int(r.z);
 #pragma unroll
     for (int k = 0; k < kMaxLevels; ++k)
       if (k == l && k < a.n_levels) {
         const LevelView& lv = a.lv[k];
-        add_region_direct(lv.code_idx, lv.code_val, lv.k_code, lv.dense_F, lv.dense_d, lv.acc, lv.zsum,
-                          __float_as_uint(r.x), __float_as_int(r.z), r.w, m_atoms, st);
+        if (lv.dense_F) {
+          if (c < lv.dense_d)
+            atomic_add_f32(&lv.acc[(unsigned long long)id * lv.dense_d + c], r.w * lv.dense_F[greg * lv.dense_d + c]);
+          else if (c == lv.dense_d)
+            atomic_add_f32(&lv.zsum[id], r.w);
+        } else if (c < lv.k_code) {
+          const int jj = lv.code_idx[greg * lv.k_code + c];
+          if (jj >= m_atoms) atomicOr(&st->data_error, 2u);
+          else if (jj >= 0)
+            atomic_add_f32(&lv.acc[(unsigned long long)id * m_atoms + jj], r.w * lv.code_val[greg * lv.k_code + c]);
+        }
       }
   }
 }
@@ -807,8 +822,11 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   StageTimer::end(kStComposite, s);
   if (a.extra_cap > 0) {
     StageTimer::begin(kStApplyExtra, s);
+    int width = 1;                            // threads per entry: the widest level's code or feature row
+    for (int l = 0; l < a.n_levels; ++l)
+      width = std::max(width, a.lv[l].dense_F ? a.lv[l].dense_d + 1 : a.lv[l].k_code);
     hipLaunchKernelGGL(k_apply_extra, dim3(std::min(2048u, (a.extra_cap + 255) / 256)), dim3(256), 0, s, a,
-                       a.m_atoms, b.status);
+                       a.m_atoms, width, b.status);
     StageTimer::end(kStApplyExtra, s);
   }
   return hipGetLastError();
