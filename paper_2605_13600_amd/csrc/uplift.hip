@@ -622,26 +622,30 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     }
   };
   // wave w walks views w, w+4, ...; the next view's offsets are loaded two
-  // views ahead and its first 64 records one view ahead of their use
+  // views ahead and its first 128 records (a group's records in a view
+  // usually fill one or two chunks) one view ahead of their use
   int v = wave;
   unsigned int ob_c = load_ob(v), ob_n = load_ob(v + 4);
   unsigned int r0_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, 0);
   unsigned int r1_c = (unsigned int)__builtin_amdgcn_readlane((int)ob_c, gn);
   float2 rc_c = load_rec(v, r0_c + (unsigned int)lane);
+  float2 rc_c2 = load_rec(v, r0_c + 64u + (unsigned int)lane);
   for (; v < a.n_views; v += 4) {
     const unsigned int ob_nn = load_ob(v + 8);
     const unsigned int r0_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, 0);
     const unsigned int r1_n = (unsigned int)__builtin_amdgcn_readlane((int)ob_n, gn);
     const float2 rc_n = load_rec(v + 4, r0_n + (unsigned int)lane);
+    const float2 rc_n2 = load_rec(v + 4, r0_n + 64u + (unsigned int)lane);
     set_starts(ob_c);
     add_chunk(r0_c + (unsigned int)lane, r1_c, rc_c);
-    for (unsigned int base = r0_c + 64u; base < r1_c; base += 64u) {
+    if (r0_c + 64u < r1_c) add_chunk(r0_c + 64u + (unsigned int)lane, r1_c, rc_c2);
+    for (unsigned int base = r0_c + 128u; base < r1_c; base += 64u) {
       const unsigned int r = base + (unsigned int)lane;
       add_chunk(r, r1_c, load_rec(v, r));
     }
     ob_c = ob_n; ob_n = ob_nn;
     r0_c = r0_n; r1_c = r1_n;
-    rc_c = rc_n;
+    rc_c = rc_n; rc_c2 = rc_n2;
   }
   add_pending();
   __syncthreads();
