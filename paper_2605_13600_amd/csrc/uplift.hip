@@ -71,7 +71,7 @@ __device__ __forceinline__ void add_region_direct(const int* code_idx, const flo
   }
 }
 
-template <int B, int WPE>
+template <int B, int WPE, int NL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_composite_blk(
     const GSplat* __restrict__ splats, const unsigned int* __restrict__ tile_start,
     const unsigned int* __restrict__ order,
@@ -86,6 +86,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ __align__(16) unsigned int s_gid[B];    // and ids
   __shared__ unsigned long long s_excl[kMaxLevels];  // per level: pixels whose region has a column
   if (st->view_overflow) return;
+  if (NL == 1) n_levels = 1;                   // one-level instance: the per-level loops fold away
   const int tile = (int)order[blockIdx.x];      // longest lists first
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const unsigned int start = tile_start[tile];
@@ -102,14 +103,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   // unused before the first batch).
   unsigned long long* s_cm = reinterpret_cast<unsigned long long*>(E);   // [kCols] pixel masks
   int* s_ci = reinterpret_cast<int*>(E + 2 * kCols);                    // [kCols][2] level, region
-  int regs[kMaxLevels];                        // the pixel's region per level (-1: none or invalid)
+  int regs[NL];                        // the pixel's region per level (-1: none or invalid)
   int ncols = 2 * n_levels;
   unsigned int spill = 0u;                     // bit l: level l has regions without a column
-  int rg0[kMaxLevels], rg1[kMaxLevels];        // per level: global ids of the two record regions (-1: none)
+  int rg0[NL], rg1[NL];        // per level: global ids of the two record regions (-1: none)
   int pkey = 0;                                // bits 2l, 2l+1: the pixel's record slot at level l (2: none)
   bool pvalid = false;                         // the pixel is in some record region
 #pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l) {
+  for (int l = 0; l < NL; ++l) {
     regs[l] = -1;
     rg0[l] = -1; rg1[l] = -1;
     if (l >= n_levels) continue;
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
   float2* rec_out = nullptr;
 #pragma unroll
-  for (int l = 0; l < kMaxLevels; ++l)
+  for (int l = 0; l < NL; ++l)
     if (rec_col && (col >> 1) == l) rec_out = args.lv[l].records;
   __syncthreads();                             // column data read before E is overwritten
 
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       if (lane < nb) {
         const unsigned int p = s_pidx[lane];
 #pragma unroll
-        for (int l = 0; l < kMaxLevels; ++l) {
+        for (int l = 0; l < NL; ++l) {
           if (l >= n_levels) break;
           const int c0 = (key0 >> (2 * l)) & 3, c1 = (key1 >> (2 * l)) & 3;
           const float w0 = (c0 == 0 ? S0 : 0.0f) + (c1 == 0 ? S1 : 0.0f);
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const int* ci = nullptr; const float* cv = nullptr; const float* dF = nullptr;
         float* ac = nullptr; float* zs = nullptr; int kc = 0, dd = 0;
 #pragma unroll
-        for (int l = 0; l < kMaxLevels; ++l)
+        for (int l = 0; l < NL; ++l)
           if (l == col_level) {
             ci = args.lv[l].code_idx; cv = args.lv[l].code_val; kc = args.lv[l].k_code;
             dF = args.lv[l].dense_F; dd = args.lv[l].dense_d; ac = args.lv[l].acc; zs = args.lv[l].zsum;
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       const bool had = gk < nb && ((contributed >> gk) & 1ull);
       const float* row = E + gk * kEStride + gq0;
 #pragma unroll
-      for (int l = 0; l < kMaxLevels; ++l) {
+      for (int l = 0; l < NL; ++l) {
         if (l >= n_levels || !((spill >> l) & 1u)) continue;
         const LevelView& lv = args.lv[l];
         const int reg = regs[l];
@@ -820,9 +821,14 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const BinArgs& b = a.bin;
   StageTimer::begin(kStComposite, s);
-  hipLaunchKernelGGL((k_composite_blk<kCompositeBatch, kCompositeWaves>), dim3(b.n_tiles), dim3(64), 0, s, b.splats, b.tile_start,
-                     b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height, a.n_levels, a.m_atoms,
-                     a, b.status);
+  if (a.n_levels == 1)
+    hipLaunchKernelGGL((k_composite_blk<kCompositeBatch, kCompositeWaves, 1>), dim3(b.n_tiles), dim3(64), 0, s,
+                       b.splats, b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width, b.cam.height,
+                       a.n_levels, a.m_atoms, a, b.status);
+  else
+    hipLaunchKernelGGL((k_composite_blk<kCompositeBatch, kCompositeWaves, kMaxLevels>), dim3(b.n_tiles), dim3(64), 0,
+                       s, b.splats, b.tile_start, b.tile_order, b.keys[b.sorted], b.tiles_x, b.cam.width,
+                       b.cam.height, a.n_levels, a.m_atoms, a, b.status);
   StageTimer::end(kStComposite, s);
   if (a.extra_cap > 0) {
     StageTimer::begin(kStApplyExtra, s);
