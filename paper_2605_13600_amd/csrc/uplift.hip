@@ -493,9 +493,10 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 // their rows (stride M+1) in LDS; wave w walks views w, w+4, ...  The
 // records of the G Gaussians in one view are one contiguous range
 // (Gaussian-major), so the wave reads it 64 records at a time, coalesced; each
-// lane finds its record's Gaussian from the range bounds held by lanes 0..G
-// and adds the record's code with LDS atomic adds.  Rows are written back
-// coalesced, Top-K and entropy read from LDS.
+// lane finds its record's Gaussian by comparing against the G range starts
+// (wave-uniform), runs of equal (Gaussian, region) records are folded, and
+// each run adds its region's code with LDS atomic adds.  Rows are written
+// back coalesced, Top-K and entropy read from LDS.
 // ---------------------------------------------------------------------------
 template <int NS>
 __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
@@ -522,12 +523,6 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   auto load_rec = [&](int v, unsigned int r) -> float2 {
     return a.records[(long long)max(0, min(v, a.n_views - 1)) * 2 * a.capacity + min(r, rec_last)];
   };
-  // Records of one 64-record chunk (record r of lane) folded per (Gaussian,
-  // region): equal (Gaussian, region) records sit two lanes apart (the same
-  // slot of consecutive pairs), so a segmented sum along lanes of equal
-  // parity folds each run of them, and the run's last lane adds its code once
-  // (fewer LDS atomics, which would otherwise collide on the same row
-  // entries).  Returns whether this lane adds, with its row, region and weight.
   // the view's record starts of Gaussians 1..G-1 as wave-uniform values (past
   // the group: never reached), so a record's Gaussian is a count of compares
   unsigned int sk[16];
@@ -536,6 +531,12 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     for (int k = 1; k < 16; ++k)
       sk[k] = k < gn ? (unsigned int)__builtin_amdgcn_readlane((int)ob, k) : 0xFFFFFFFFu;
   };
+  // Records of one 64-record chunk (record r of lane) folded per (Gaussian,
+  // region): equal (Gaussian, region) records sit two lanes apart (the same
+  // slot of consecutive pairs), so a segmented sum along lanes of equal
+  // parity folds each run of them, and the run's last lane adds its code once
+  // (fewer LDS atomics, which would otherwise collide on the same row
+  // entries).  Returns whether this lane adds, with its row, region and weight.
   auto fold = [&](unsigned int r, unsigned int r1, float2 rc, int& g, int& reg, float& w) -> bool {
     g = 0;                                     // last Gaussian whose range starts at or before r
 #pragma unroll
