@@ -327,8 +327,12 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
   __syncthreads();
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
-  for (long long i = i0 + threadIdx.x; i < i1; i += kCountThreads) {
-    const GSplat g = splats[i];
+  long long i = i0 + threadIdx.x;
+  GSplat g_next;                                     // the thread's next splat, loaded a round ahead
+  if (i < i1) g_next = splats[i];
+  for (; i < i1; i += kCountThreads) {
+    const GSplat g = g_next;
+    if (i + kCountThreads < i1) g_next = splats[i + kCountThreads];
     if (g.bx0 > g.bx1) continue;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
@@ -391,8 +395,12 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, lon
   __syncthreads();
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
-  for (long long i = i0 + threadIdx.x; i < i1; i += kCountThreads) {
-    const GSplat g = splats[i];
+  long long i = i0 + threadIdx.x;
+  GSplat g_next;                                     // the thread's next splat, loaded a round ahead
+  if (i < i1) g_next = splats[i];
+  for (; i < i1; i += kCountThreads) {
+    const GSplat g = g_next;
+    if (i + kCountThreads < i1) g_next = splats[i + kCountThreads];
     if (g.bx0 > g.bx1) continue;
     const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
