@@ -896,11 +896,30 @@ __global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __
 // first (as k_tile_order).  Thread i owns tiles [i c, i c + c): it reads
 // its lengths, and after the scan of the 1024 chunk sums rewrites them as
 // starts, keeping each tile's length bucket in LDS for the placement.
+// Exclusive scan of one value per thread over a 1024-thread workgroup:
+// shuffle scans inside the waves, then each thread adds the totals of the
+// waves before it (16 wave totals in LDS; two barriers).
+__device__ __forceinline__ unsigned int block_exclusive_scan_1024(unsigned int x, unsigned int* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned int inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned int v = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned int before = 0u;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  __syncthreads();                             // wsum free for the next scan
+  return before + inc - x;
+}
+
 __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restrict__ tile_start, int n_tiles,
                                                           int sort_cap, unsigned int* __restrict__ big_tiles,
                                                           unsigned int* __restrict__ order, Status* st) {
   __shared__ unsigned int h[kOrderBuckets];
-  __shared__ unsigned int part[1024];
+  __shared__ unsigned int wsum[16];
   extern __shared__ unsigned short s_b[];      // [n_tiles] length buckets
   const int tid = threadIdx.x;
   for (int b = tid; b < kOrderBuckets; b += 1024) h[b] = 0u;
@@ -908,15 +927,8 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
   const int t0 = min(n_tiles, tid * c), t1 = min(n_tiles, t0 + c);
   unsigned int sum = 0u;
   for (int t = t0; t < t1; ++t) sum += tile_start[t];
-  part[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const unsigned int v = tid >= o ? part[tid - o] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  unsigned int run = part[tid] - sum;
+  unsigned int run = block_exclusive_scan_1024(sum, wsum);   // (the bucket clears above are before its barriers)
+  if (tid == 1023) tile_start[n_tiles] = run + sum;
   for (int t = t0; t < t1; ++t) {
     const unsigned int L = tile_start[t];
     tile_start[t] = run;
@@ -926,21 +938,11 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
     atomicAdd(&h[b], 1u);
     if (L > (unsigned int)sort_cap && !st->view_overflow) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
   }
-  if (tid == 1023) tile_start[n_tiles] = part[1023];
   __syncthreads();
   if (!order) return;
   // exclusive scan of the buckets: two per thread, then across threads
   const unsigned int c0 = h[2 * tid], c1 = h[2 * tid + 1];
-  part[tid] = c0 + c1;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const unsigned int v = tid >= o ? part[tid - o] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  const unsigned int before = part[tid] - (c0 + c1);
-  __syncthreads();
+  const unsigned int before = block_exclusive_scan_1024(c0 + c1, wsum);
   h[2 * tid] = before;
   h[2 * tid + 1] = before + c0;
   __syncthreads();
