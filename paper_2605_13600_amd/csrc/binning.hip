@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
   long long i = i0 + threadIdx.x;
-  GSplat g_next;                                     // the thread's next splat, loaded a round ahead
+  GSplat g_next;                                     // the thread's next splat, loaded an iteration ahead
   if (i < i1) g_next = splats[i];
   for (; i < i1; i += kCountThreads) {
     const GSplat g = g_next;
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, lon
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
   long long i = i0 + threadIdx.x;
-  GSplat g_next;                                     // the thread's next splat, loaded a round ahead
+  GSplat g_next;                                     // the thread's next splat, loaded an iteration ahead
   if (i < i1) g_next = splats[i];
   for (; i < i1; i += kCountThreads) {
     const GSplat g = g_next;
