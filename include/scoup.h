@@ -128,9 +128,14 @@ int64_t scoup_required_pair_capacity(void);
  *   n_contrib     device uint64 [1] or NULL; receives (+=) the number of
  *                 Gaussian-pixel contributions (terms e > 0) composited
  * Returns SCOUP_E_WORKSPACE if the workspace is too small or a view's pair
- * count exceeds pair_capacity (acc is then incomplete; call again with
- * scoup_required_pair_capacity()), SCOUP_E_DATA if a region id is >= the
- * view's region count or a code atom index is >= m.                         */
+ * count exceeds pair_capacity (call again with scoup_required_pair_capacity()),
+ * SCOUP_E_DATA if a region id is >= the view's region count or a code atom
+ * index is >= m.  After SCOUP_E_WORKSPACE with accumulate = 0, acc holds
+ * unspecified values (a successful call overwrites it); with accumulate = 1
+ * every view's pair count is checked before anything is written (one more
+ * pass over the Gaussians per 32 views), so acc is left unchanged and the
+ * same call can simply be repeated with a larger capacity.  After
+ * SCOUP_E_DATA acc is unspecified in both modes.                            */
 scoup_status scoup_uplift_accumulate(const scoup_gaussians* g, const scoup_views* views,
                                      float* acc, int32_t accumulate, int64_t pair_capacity,
                                      int32_t view_batch, void* ws, size_t ws_bytes,
@@ -253,14 +258,23 @@ size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_ca
                                              int32_t m_atoms, int32_t dim, int64_t pair_capacity);
 
 /* Backward of render + decode (float32) for a loss with gradient
- * G = dL/dfeatures on one camera:
+ * G = dL/dfeatures on one camera (Eq. 7 and Eq. 8 differentiated):
  *   grad_codebook[j*dim + d] += sum_p coeff_map[p*m + j] G[p*dim + d]
  *   grad_topk_val[i*k + s]   += sum_p e_i(v,p) (G(p) C^T)[topk_idx[i*k + s]]
  * Indices and geometry receive no gradient.  coeff_map is the float32 map of
- * scoup_render_coeff (coeff_scale 1) for the same inputs.
+ * scoup_render_coeff (coeff_scale 1) for the same inputs.  Every sum is taken
+ * in a fixed order (partial sums per pixel chunk and per (Gaussian, 8x8
+ * block) pair, then added in order), so results are bit-reproducible.
+ *   topk_idx/val   device [n*k], 1 <= k <= 16;  1 <= m_atoms <= 512;  1 <= dim <= 4096
  *   grad_features  device float32 [H*W*dim]
  *   grad_topk_val  device float32 [n*k]       (accumulated)
- *   grad_codebook  device float32 [m_atoms*dim] (accumulated)              */
+ *   grad_codebook  device float32 [m_atoms*dim] (accumulated)
+ *   ws, ws_bytes   at least scoup_render_backward_workspace_bytes(n, cam, m_atoms,
+ *                  dim, pair_capacity) (0 = 16 pairs per Gaussian); the pair
+ *                  capacity is derived from ws_bytes
+ * Returns SCOUP_E_WORKSPACE when the view has more (Gaussian, block) pairs
+ * than the workspace holds (scoup_required_pair_capacity() gives the count);
+ * the gradient buffers are then left unchanged.                             */
 scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk_idx,
                                    const float* topk_val, int32_t k, int32_t m_atoms,
                                    const scoup_camera* cam, const float* coeff_map,
@@ -297,6 +311,17 @@ int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
  * scoup_views_in_flight returns the current value. */
 void scoup_set_views_in_flight(int32_t k);
 int32_t scoup_views_in_flight(void);
+
+/* Deferred further-region entries of the uplift: an 8x8 block whose pixels
+ * fall into more regions (over all levels) than its two record regions keeps
+ * the weights of the others as (Gaussian, level, region, weight) entries in a
+ * per-view buffer of the workspace, added to the accumulator after the view;
+ * once that buffer is full the compositing adds such weights to the
+ * accumulator directly with atomics (same sums, other float rounding order).
+ * scoup_set_deferred_entry_limit(n) caps the buffer at n entries per view
+ * (n <= 0 restores the workspace's own capacity), so the direct path can be
+ * exercised on small inputs.  Process-wide, read at each call.              */
+void scoup_set_deferred_entry_limit(int64_t n);
 
 /* ---------------------------------------------------------------------------
  * Several semantic levels in one pass (Sec. 4.1: SAM masks at three

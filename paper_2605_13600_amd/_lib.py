@@ -73,6 +73,7 @@ SIGNATURES = {
     "scoup_stage_stats": (C.c_int32, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "scoup_set_views_in_flight": (None, [C.c_int32]),
     "scoup_views_in_flight": (C.c_int32, []),
+    "scoup_set_deferred_entry_limit": (None, [C.c_int64]),
     "scoup_last_error": (C.c_char_p, []),
     "scoup_version": (C.c_char_p, []),
 }

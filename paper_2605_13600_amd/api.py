@@ -286,6 +286,13 @@ def views_in_flight() -> int:
     return int(L.load().scoup_views_in_flight())
 
 
+def set_deferred_entry_limit(n: int) -> None:
+    """Cap the uplift's per-view buffer of deferred further-region entries at
+    ``n`` entries (0 = the workspace's capacity); past it the compositing adds
+    those weights to the accumulator directly."""
+    L.load().scoup_set_deferred_entry_limit(int(n))
+
+
 def uplift(g: DeviceGaussians, views: DeviceViews, k: int, stream=None, workspace=None,
            pair_capacity: int = 0, view_batch: int = 0, acc: Optional[torch.Tensor] = None):
     """Algorithm 1: accumulate over all views, then Top-K (fused into the last

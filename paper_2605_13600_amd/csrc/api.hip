@@ -39,7 +39,7 @@ int tiles_of(int w, int h, int shift = 4) {
 
 // Workspace layout of one binning pass (+ the uplift's per-view offsets and records).
 struct BinLayout {
-  size_t status, splats, offsets, scan_part, tile_start, big_tiles, tile_order, bin_hist, radix_hist, tile_ids[2],
+  size_t status, vtot, splats, offsets, scan_part, tile_start, big_tiles, tile_order, bin_hist, radix_hist, tile_ids[2],
       keys[2], records, extra, total;
   unsigned int extra_cap;
   bool counting;
@@ -50,6 +50,7 @@ BinLayout bin_layout(int64_t n, int max_tiles, int64_t cap, int off_views, int r
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   size_t off = 0;
   L.status = off; off = align256(off + sizeof(Status));
+  L.vtot = off; off = align256(off + 8 * (size_t)kCountCams);
   L.splats = off; off = align256(off + sizeof(GSplat) * nn);
   L.offsets = off; off = align256(off + 4 * (size_t)(n + 1) * (size_t)off_views);
   const long long sparts =
@@ -83,6 +84,27 @@ int64_t capacity_for(int64_t n, int max_tiles, size_t bytes) {
   return std::min<int64_t>(std::max<int64_t>(cap, 0), 0x7fffffffLL);
 }
 
+// largest pair capacity whose single-view layout plus `per_pair` more bytes
+// per pair fits in `bytes` (0 if none)
+int64_t capacity_for_extra(int64_t n, int max_tiles, size_t bytes, size_t per_pair) {
+  auto need = [&](int64_t cap) {
+    return bin_layout(n, max_tiles, cap, 1, 0, false).total + align256(per_pair * (size_t)cap);
+  };
+  if (need(1) > bytes) return 0;
+  int64_t lo = 1, hi = 0x7fffffffLL;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (need(mid) <= bytes) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// render backward: transposed codebook, dL/dW_hat map, dL/dC chunk partials
+size_t render_bwd_fixed_bytes(size_t P, int m, int d) {
+  return align256(decode_codebook_bytes(d, m, SCOUP_F32)) + align256(4 * P * (size_t)m) +
+         align256(4 * (size_t)gemm_at_b_chunks((long long)P, m, d) * (size_t)m * (size_t)d);
+}
+
 int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
   int mt = 1;
   for (int i = 0; i < v->n_views; ++i) mt = std::max(mt, tiles_of(v->cams[i].width, v->cams[i].height, 3));
@@ -94,6 +116,7 @@ int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
 // further sets of per-view binning buffers follow the first layout.
 constexpr int kLanes = 4;                     // workspace sized for this many; the setting below may use fewer
 int g_views_in_flight = kLanes;
+unsigned int g_extra_cap_limit = 0;           // 0: the layout's deferred-entry capacity
 BinLayout uplift_layout(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
   return bin_layout(n, mt, cap, vb, vb * n_levels, true);
 }
@@ -154,6 +177,7 @@ void fill_bin(BinArgs& b, const scoup_gaussians* g, char* base, const BinLayout&
   b.capacity = capacity;
   b.status = reinterpret_cast<Status*>(base + L.status);
   b.sorted = 0;
+  b.pair_index = 0;
 }
 
 std::once_flag g_lds_once;
@@ -289,6 +313,10 @@ void scoup_set_views_in_flight(int32_t k) { g_views_in_flight = std::max(1, std:
 
 int32_t scoup_views_in_flight(void) { return g_views_in_flight; }
 
+void scoup_set_deferred_entry_limit(int64_t n) {
+  g_extra_cap_limit = n <= 0 ? 0u : (unsigned int)std::min<int64_t>(n, 0xffffffffLL);
+}
+
 const char* scoup_last_error(void) { return g_err.c_str(); }
 
 const char* scoup_version(void) { return "libscoup 0.1 gfx950"; }
@@ -352,9 +380,32 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   }
   HIP_TRY(ensure_lds_limits());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  if (accumulate && g->n > 0 && v->n_views > 0) {
+    // A resumed call must leave acc as it was if a view exceeds the pair
+    // capacity: every view's pair count is found (one pass over the Gaussians
+    // per kCountCams views, the projection's own box arithmetic) and checked
+    // before anything is written.
+    unsigned long long* vt = reinterpret_cast<unsigned long long*>(base + L.vtot);
+    std::vector<unsigned long long> tot((size_t)v->n_views, 0ull);
+    for (int v0 = 0; v0 < v->n_views; v0 += kCountCams) {
+      CamBatch cb{};
+      cb.n = std::min(kCountCams, v->n_views - v0);
+      for (int j = 0; j < cb.n; ++j) cb.c[j] = to_dev(v->cams[v0 + j]);
+      HIP_TRY(hipMemsetAsync(vt, 0, 8 * (size_t)kCountCams, s));
+      HIP_TRY(launch_count_view_pairs(g->means, g->log_scales, g->quats, g->opacities, g->n, cb, 3, vt, s));
+      HIP_TRY(hipMemcpyAsync(tot.data() + v0, vt, 8 * (size_t)cb.n, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    const unsigned long long mx = *std::max_element(tot.begin(), tot.end());
+    if (mx > (unsigned long long)pair_capacity) {
+      g_required_pairs = (int64_t)std::min<unsigned long long>(mx, 0x7fffffffull);
+      return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(pair_capacity) + " exceeded; need " +
+                                         std::to_string(mx) + " (acc unchanged)");
+    }
+  }
   SideStreams* side = nullptr;
   if (lanes > 1) HIP_TRY(side_streams(&side));
-  char* base = static_cast<char*>(ws);
   const BinLayout L2 = uplift_lane2_layout(g->n, mt, pair_capacity);
   char* lane_base[kLanes] = {base};
   for (int k = 1; k < lanes; ++k) lane_base[k] = base + align256(L.total) + (size_t)(k - 1) * align256(L2.total);
@@ -371,11 +422,11 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   UpliftViewArgs a[kLanes] = {};
   fill_bin(a[0].bin, g, base, L, pair_capacity, 3, kSortCap);
   a[0].extra = reinterpret_cast<float4*>(base + L.extra);
-  a[0].extra_cap = L.extra_cap;
+  a[0].extra_cap = g_extra_cap_limit ? std::min(L.extra_cap, g_extra_cap_limit) : L.extra_cap;
   for (int k = 1; k < lanes; ++k) {
     fill_bin(a[k].bin, g, lane_base[k], L2, pair_capacity, 3, kSortCap);
     a[k].extra = reinterpret_cast<float4*>(lane_base[k] + L2.extra);
-    a[k].extra_cap = L2.extra_cap;
+    a[k].extra_cap = g_extra_cap_limit ? std::min(L2.extra_cap, g_extra_cap_limit) : L2.extra_cap;
   }
   unsigned int* off_all = a[0].bin.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
@@ -758,10 +809,12 @@ scoup_status scoup_relevancy(const void* coeff, scoup_dtype in_dtype, float coef
 
 size_t scoup_render_backward_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t m_atoms,
                                               int32_t dim, int64_t pair_capacity) {
-  if (!cam || n_gaussians < 0 || m_atoms < 1 || dim < 1) return 0;
+  if (!cam || n_gaussians < 0 || m_atoms < 1 || dim < 1 || cam->width <= 0 || cam->height <= 0) return 0;
   const size_t P = (size_t)cam->width * cam->height;
-  const size_t pre = align256(decode_codebook_bytes(dim, m_atoms, SCOUP_F32)) + align256(4 * P * m_atoms);
-  return pre + scoup_render_workspace_bytes(n_gaussians, cam, pair_capacity);
+  if (pair_capacity <= 0) pair_capacity = std::max<int64_t>(16 * n_gaussians, 1 << 16);
+  const int mt = tiles_of(cam->width, cam->height, 3);
+  return render_bwd_fixed_bytes(P, m_atoms, dim) + bin_layout(n_gaussians, mt, pair_capacity, 1, 0, false).total +
+         align256(4 * (size_t)kBwdKMax * (size_t)pair_capacity);
 }
 
 scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
@@ -774,7 +827,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   if (st != SCOUP_OK) return st;
   if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
   if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
-  if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
+  if (k < 1 || k > kBwdKMax) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
   if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
   if (dim < 1 || dim > 4096) return fail(SCOUP_E_ARG, "dim must be in [1, 4096]");
   if (!coeff_map || !codebook || !grad_features || !grad_codebook)
@@ -785,20 +838,35 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   const long long P = (long long)cam->width * cam->height;
   const size_t prep_b = align256(decode_codebook_bytes(dim, m_atoms, SCOUP_F32));
   const size_t dw_b = align256(4 * (size_t)P * m_atoms);
+  const size_t fixed = render_bwd_fixed_bytes((size_t)P, m_atoms, dim);
   const int shift = 3;
   const int mt = tiles_of(cam->width, cam->height, shift);
-  if (ws_bytes < prep_b + dw_b) return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
-  const long long capacity = capacity_for(g->n, mt, ws_bytes - prep_b - dw_b);
+  const long long capacity =
+      ws_bytes > fixed ? capacity_for_extra(g->n, mt, ws_bytes - fixed, 4 * (size_t)kBwdKMax) : 0;
   if (capacity < 1) {
-    g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
+    g_required_pairs = std::max<int64_t>(16 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
   }
   const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0, false);
   char* base = static_cast<char*>(ws);
   void* prep = base;
   float* dW = reinterpret_cast<float*>(base + prep_b);
-  char* bbase = base + prep_b + dw_b;
+  float* gemm_part = reinterpret_cast<float*>(base + prep_b + dw_b);
+  char* bbase = base + fixed;
+  float* pair_part = reinterpret_cast<float*>(bbase + L.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  RenderBwdArgs a{};
+  fill_bin(a.bin, g, bbase, L, capacity, shift, kSortCap);
+  a.bin.cam = to_dev(*cam);
+  a.bin.tiles_x = (cam->width + 7) / 8;
+  a.bin.n_tiles = mt;
+  a.bin.pair_index = 1;
+  a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
+  a.dW = dW; a.pair_part = pair_part; a.grad_val = grad_topk_val;
+  Status* status = a.bin.status;
+  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  // binning first: its pair-capacity check gates every write to the caller's gradients
+  HIP_TRY(launch_bin_view(a.bin, s));
   // dW = G C^T : K = dim, N = m_atoms, B(k, n) = C[n * dim + k]
   HIP_TRY(launch_prep_codebook(codebook, dim, m_atoms, SCOUP_F32, prep, nullptr, s, 1));
   DecodeArgs d{};
@@ -806,16 +874,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   d.in_dtype = SCOUP_F32; d.out_dtype = SCOUP_F32; d.codebook_prep = prep; d.cb_scale = nullptr;
   d.out_mul = 1.0f; d.out = dW; d.ldo = m_atoms;
   HIP_TRY(launch_decode(d, s, kStBwdGemm));
-  HIP_TRY(launch_gemm_at_b(coeff_map, grad_features, P, m_atoms, dim, grad_codebook, s));
-  RenderBwdArgs a{};
-  fill_bin(a.bin, g, bbase, L, capacity, shift, kSortCap);
-  a.bin.cam = to_dev(*cam);
-  a.bin.tiles_x = (cam->width + 7) / 8;
-  a.bin.n_tiles = mt;
-  a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
-  a.dW = dW; a.grad_val = grad_topk_val;
-  Status* status = a.bin.status;
-  HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
+  HIP_TRY(launch_gemm_at_b(coeff_map, grad_features, P, m_atoms, dim, gemm_part, grad_codebook, status, s));
   HIP_TRY(launch_render_bwd_view(a, s));
   Status h{};
   HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -824,7 +883,7 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
   if (h.any_overflow) {
     g_required_pairs = (int64_t)h.max_pairs;
     return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(capacity) + " exceeded; need " +
-                                       std::to_string(h.max_pairs));
+                                       std::to_string(h.max_pairs) + " (gradients unchanged)");
   }
   return SCOUP_OK;
 }

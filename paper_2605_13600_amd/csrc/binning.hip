@@ -44,48 +44,56 @@ struct CullRecords {
 // ---------------------------------------------------------------------------
 // projection (one thread per Gaussian), FP64 arithmetic, FP32 storage
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_project(
-    const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ opacities, long long n,
-    CamDev cam, int tile_shift, GSplat* __restrict__ out, unsigned int* __restrict__ n_tiles) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  GSplat s;
+// Inputs of one Gaussian, loaded once (one memory latency per thread).
+struct GaussIn {
+  double mx, my, mz;
+  float o, q[4], ls[3];
+};
+
+__device__ __forceinline__ GaussIn load_gauss(const float* __restrict__ means, const float* __restrict__ log_scales,
+                                              const float* __restrict__ quats, const float* __restrict__ opacities,
+                                              long long i) {
+  GaussIn g;
+  g.mx = means[3 * i + 0]; g.my = means[3 * i + 1]; g.mz = means[3 * i + 2];
+  g.o = opacities[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g.q[k] = quats[4 * i + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.ls[k] = log_scales[3 * i + k];
+  return g;
+}
+
+// The EWA splat of one Gaussian in one camera and the number of
+// (1 << tile_shift)-pixel blocks its box covers (0 = invisible).  Every
+// operation is a separately rounded IEEE double operation (no fused
+// multiply-adds), so any kernel that calls this gets bit-identical boxes:
+// the pair count checked before a resumed uplift is the one its views use.
+__device__ __forceinline__ unsigned int project_splat(const GaussIn& gi, const CamDev& cam, int tile_shift,
+                                                      GSplat& s) {
+#pragma clang fp contract(off)
   s.ix = 0; s.iy = 0; s.fx = 0.f; s.fy = 0.f;
   s.l00 = 0.f; s.l10 = 0.f; s.l11 = 0.f; s.opacity = 0.f;
   s.bx0 = 1; s.bx1 = 0; s.by0 = 1; s.by1 = 0;   // empty box = invisible
   s.depth_bits = 0u; s.live = 0u;
-  unsigned int nt = 0;
-
-  // every input is loaded up front: one memory latency per thread, not one per use
-  const double mx = means[3 * i + 0], my = means[3 * i + 1], mz = means[3 * i + 2];
-  const float o_in = opacities[i];
-  const float q_in[4] = {quats[4 * i + 0], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
-  const float ls_in[3] = {log_scales[3 * i + 0], log_scales[3 * i + 1], log_scales[3 * i + 2]};
-  asm volatile("" ::"v"(o_in), "v"(q_in[0]), "v"(q_in[1]), "v"(q_in[2]), "v"(q_in[3]), "v"(ls_in[0]),
-               "v"(ls_in[1]), "v"(ls_in[2]));   // keeps the loads ahead of the visibility test
-  double x, y, z;
-  {
-    // Camera point p = R mu + t summed left to right without fused multiply-adds,
-    // so the view depth (and its float32 sort key) is reproducible exactly.
-#pragma clang fp contract(off)
-    x = (double)cam.R[0] * mx + (double)cam.R[1] * my + (double)cam.R[2] * mz + (double)cam.t[0];
-    y = (double)cam.R[3] * mx + (double)cam.R[4] * my + (double)cam.R[5] * mz + (double)cam.t[1];
-    z = (double)cam.R[6] * mx + (double)cam.R[7] * my + (double)cam.R[8] * mz + (double)cam.t[2];
-  }
-  const double o = o_in;
+  // camera point p = R mu + t summed left to right (the view depth and its
+  // float32 sort key are reproducible exactly)
+  const double mx = gi.mx, my = gi.my, mz = gi.mz;
+  const double x = (double)cam.R[0] * mx + (double)cam.R[1] * my + (double)cam.R[2] * mz + (double)cam.t[0];
+  const double y = (double)cam.R[3] * mx + (double)cam.R[4] * my + (double)cam.R[5] * mz + (double)cam.t[1];
+  const double z = (double)cam.R[6] * mx + (double)cam.R[7] * my + (double)cam.R[8] * mz + (double)cam.t[2];
+  const double o = gi.o;
   const double lo = log(255.0 * o);
-  if (!(z > (double)cam.near_z) || !(lo >= 0.0)) { out[i] = s; n_tiles[i] = 0u; return; }
+  if (!(z > (double)cam.near_z) || !(lo >= 0.0)) return 0u;
 
   // 3D covariance Sigma = R diag(exp(2 s)) R^T from the normalised quaternion
-  double qw = q_in[0], qx = q_in[1], qy = q_in[2], qz = q_in[3];
+  double qw = gi.q[0], qx = gi.q[1], qy = gi.q[2], qz = gi.q[3];
   const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= qn; qx *= qn; qy *= qn; qz *= qn;
   const double Rq[3][3] = {
       {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
       {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
       {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  const double s2[3] = {exp(2.0 * (double)ls_in[0]), exp(2.0 * (double)ls_in[1]), exp(2.0 * (double)ls_in[2])};
+  const double s2[3] = {exp(2.0 * (double)gi.ls[0]), exp(2.0 * (double)gi.ls[1]), exp(2.0 * (double)gi.ls[2])};
   double S[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -119,9 +127,7 @@ __global__ __launch_bounds__(256) void k_project(
   const double det = sxx * syy - sxy * sxy;
   const double mux = fx * x / z + (double)cam.cx;
   const double muy = fy * y / z + (double)cam.cy;
-  if (!(det > 0.0) || !(fabs(mux) < 1073741824.0) || !(fabs(muy) < 1073741824.0)) {
-    out[i] = s; n_tiles[i] = 0u; return;
-  }
+  if (!(det > 0.0) || !(fabs(mux) < 1073741824.0) || !(fabs(muy) < 1073741824.0)) return 0u;
   // conservative pixel box of {alpha >= 1/255}: |dx| <= sqrt(2 ln(255 o) Sxx)
   const double r2 = 2.0 * lo;
   const double hx = sqrt(r2 * sxx), hy = sqrt(r2 * syy);
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(256) void k_project(
   double y0 = ceil(muy - hy - 0.5) - 1.0, y1 = floor(muy + hy - 0.5) + 1.0;
   x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
   x1 = fmin(x1, (double)(cam.width - 1)); y1 = fmin(y1, (double)(cam.height - 1));
-  if (!(x0 <= x1) || !(y0 <= y1)) { out[i] = s; n_tiles[i] = 0u; return; }
+  if (!(x0 <= x1) || !(y0 <= y1)) return 0u;
 
   // scaled factor of the conic: q = (l00 dx + l10 dy)^2 + (l11 dy)^2 = log2(e)/2 d^T conic d
   const double ks = 0.84932180028801904272;   // sqrt(log2(e) / 2)
@@ -145,7 +151,23 @@ __global__ __launch_bounds__(256) void k_project(
   s.depth_bits = __float_as_uint((float)z);
   const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
   const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
-  {
+  return (unsigned int)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+}
+
+__global__ __launch_bounds__(256) void k_project(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ opacities, long long n,
+    CamDev cam, int tile_shift, GSplat* __restrict__ out, unsigned int* __restrict__ n_tiles) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const GaussIn gi = load_gauss(means, log_scales, quats, opacities, i);
+  asm volatile("" ::"v"(gi.o), "v"(gi.q[0]), "v"(gi.q[1]), "v"(gi.q[2]), "v"(gi.q[3]), "v"(gi.ls[0]),
+               "v"(gi.ls[1]), "v"(gi.ls[2]));   // keeps the loads ahead of the visibility test
+  GSplat s;
+  const unsigned int nt = project_splat(gi, cam, tile_shift, s);
+  if (nt > 0u) {
+    const int tx0 = s.bx0 >> tile_shift, tx1 = s.bx1 >> tile_shift;
+    const int ty0 = s.by0 >> tile_shift, ty1 = s.by1 >> tile_shift;
     const BlockCull bc(s, tile_shift, cam.width, cam.height);
     unsigned int live = 0u;
     int r = 0;
@@ -155,8 +177,46 @@ __global__ __launch_bounds__(256) void k_project(
     s.live = live;
   }
   out[i] = s;
-  nt = (unsigned int)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   n_tiles[i] = nt;
+}
+
+// Pairs (Gaussian, block) of up to kCountCams views in one pass over the
+// Gaussians: totals[v] += sum_i (blocks of i's box in view v), the counts the
+// views' own projections will give (same device function).  Per-view sums are
+// wave-reduced, then gathered in LDS, then one atomic per (workgroup, view).
+__global__ __launch_bounds__(256) void k_count_view_pairs(const float* __restrict__ means,
+                                                          const float* __restrict__ log_scales,
+                                                          const float* __restrict__ quats,
+                                                          const float* __restrict__ opacities, long long n,
+                                                          CamBatch cams, int tile_shift,
+                                                          unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long s_tot[kCountCams];
+  if (threadIdx.x < kCountCams) s_tot[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (long long i0 = (long long)blockIdx.x * 256; i0 < n; i0 += (long long)gridDim.x * 256) {
+    const long long i = i0 + threadIdx.x;
+    const bool ok = i < n;
+    const GaussIn gi = load_gauss(means, log_scales, quats, opacities, ok ? i : 0);
+    for (int v = 0; v < cams.n; ++v) {
+      GSplat s;
+      unsigned long long c = ok ? (unsigned long long)project_splat(gi, cams.c[v], tile_shift, s) : 0ull;
+      for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (lane == 0 && c) atomicAdd(&s_tot[v], c);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cams.n && s_tot[threadIdx.x]) atomicAdd(&totals[threadIdx.x], s_tot[threadIdx.x]);
+}
+
+hipError_t launch_count_view_pairs(const float* means, const float* log_scales, const float* quats,
+                                   const float* opacities, long long n, const CamBatch& cams, int tile_shift,
+                                   unsigned long long* totals, hipStream_t s) {
+  if (n <= 0 || cams.n <= 0) return hipSuccess;
+  const long long nb = std::min<long long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_count_view_pairs, dim3((unsigned)nb), dim3(256), 0, s, means, log_scales, quats, opacities,
+                     n, cams, tile_shift, totals);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,7 +1073,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     StageTimer::begin(kStEmit, s);
     hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, a.splats, a.n, a.tiles_x, a.n_tiles, a.tile_shift,
                        a.cam.width, a.cam.height, (const unsigned int*)a.offsets, a.tile_ids[0], a.keys[0],
-                       a.n_cull_records > 0 ? 1 : 0, a.status);
+                       (a.n_cull_records > 0 || a.pair_index) ? 1 : 0, a.status);
     StageTimer::end(kStEmit, s);
   }
   StageTimer::begin(kStSortBig, s);
@@ -1034,7 +1094,7 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
                        a.splats, a.n, a.tiles_x, a.n_tiles,
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, (const unsigned int*)a.bin_hist,
                        (const unsigned int*)a.tile_start, a.keys[0],
-                       a.n_cull_records > 0 ? (const unsigned int*)a.offsets : nullptr, a.status);
+                       (a.n_cull_records > 0 || a.pair_index) ? (const unsigned int*)a.offsets : nullptr, a.status);
     a.sorted = 0;
     sort_lists(a, s, true);
     StageTimer::end(kStSortBig, s);

@@ -44,9 +44,23 @@ struct BinArgs {
   long long capacity;
   Status* status;
   int sorted;              // set by launch_bin_view: which buffer holds the sorted pairs
+  int pair_index;          // leave each Gaussian's first pair index in its splat (also done when
+                           // n_cull_records > 0): pair (i, b) has slot offsets[i] + b's index in i's box
 };
 
 hipError_t launch_bin_view(BinArgs& a, hipStream_t s);
+
+// Pair counts of up to kCountCams views in one pass: totals[v] += pairs of
+// view v (the counts launch_bin_view's scan will find), for a capacity check
+// before anything is written.
+constexpr int kCountCams = 32;
+struct CamBatch {
+  CamDev c[kCountCams];
+  int n;
+};
+hipError_t launch_count_view_pairs(const float* means, const float* log_scales, const float* quats,
+                                   const float* opacities, long long n, const CamBatch& cams, int tile_shift,
+                                   unsigned long long* totals, hipStream_t s);
 int radix_passes(int n_tiles);
 long long radix_blocks(long long capacity);
 long long scan_blocks(long long n);
@@ -147,19 +161,25 @@ int relevancy_groups(int q);
 size_t relevancy_frag_bytes(int m, int q, int in_dtype);
 hipError_t launch_relevancy(const RelevancyArgs& a, hipStream_t s);
 
+constexpr int kBwdKMax = 16;        // Top-K slots the render backward supports
+constexpr int kGemmMaxParts = 512;  // chunk x tile partial products of the dL/dC GEMM (<= 32 MB)
 struct RenderBwdArgs {
-  BinArgs bin;
+  BinArgs bin;                 // binned (launch_bin_view) with pair_index set
   const int* topk_idx;
   const float* topk_val;
   int k, m_atoms;
   const float* dW;             // [P x m] float32 gradient of the coefficient map
+  float* pair_part;            // [capacity x k] per-(Gaussian, block) partial sums (workspace)
   float* grad_val;             // [N x k] float32, accumulated
 };
 hipError_t launch_render_bwd_view(RenderBwdArgs& a, hipStream_t s);
 hipError_t render_bwd_set_lds_limits();
-// grad_C[m x d] += coeff^T [m x P] * G [P x d], float32 MFMA, split over pixels
-hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int m, int d, float* grad_C,
-                            hipStream_t s);
+// grad_C[m x d] += coeff^T [m x P] * G [P x d], float32 MFMA: per-chunk partial
+// products in `part` (gemm_at_b_chunks(P, m, d) x m x d floats), then summed in
+// chunk order; nothing is added when st reports a pair overflow.
+int gemm_at_b_chunks(long long P, int m, int d);
+hipError_t launch_gemm_at_b(const float* coeff, const float* G, long long P, int m, int d, float* part,
+                            float* grad_C, const Status* st, hipStream_t s);
 hipError_t decode_set_lds_limits();
 hipError_t launch_topk(const float* acc, long long n, int m, int k, int* idx, float* val, hipStream_t s);
 hipError_t launch_entropy(const float* acc, long long n, int m, float* out, hipStream_t s);

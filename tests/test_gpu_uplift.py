@@ -126,6 +126,95 @@ def test_workspace_retry_path_and_view_batches():
         assert abs(nc - ref.n_contrib) <= ref.count_slack
 
 
+@pytest.mark.parametrize("vb", [1, 0])
+def test_resumed_call_over_capacity_leaves_acc_unchanged(vb):
+    """Eq. 5 sums over views, so a second call with accumulate=1 resumes over
+    further views.  When that call's pair capacity is too small it reports
+    SCOUP_E_WORKSPACE before writing anything: acc is bit for bit what it was.
+    Repeated with exactly the capacity it asked for, it succeeds (the count
+    checked up front is the count its views use) and equals one call over all
+    views."""
+    require_gpu()
+    import ctypes as C
+    from paper_2605_13600_amd import _lib as L
+    sc = sg.make_scene("tiny")
+    lib = L.load()
+    dg = P.gaussians_to_device(sc.gaussians)
+    full, _ = P.uplift_accumulate(dg, P.views_to_device(sc.views))
+    a, _ = P.uplift_accumulate(dg, P.views_to_device(sg.subset_views(sc.views, [0, 1])))
+    before = a.clone()
+    dv2 = P.views_to_device(sg.subset_views(sc.views, [2, 3]))
+    gs, vs = dg.struct(), dv2.struct()
+    ws = P.api.Workspace()
+    cap = 16
+    buf = ws.get(lib.scoup_uplift_workspace_bytes(dg.n, C.byref(vs), cap, vb))
+    st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), a.data_ptr(), 1, cap, vb, buf.data_ptr(),
+                                     buf.numel(), None, None)
+    torch.cuda.synchronize()
+    need = int(lib.scoup_required_pair_capacity())
+    assert st == L.E_WORKSPACE and need > cap, (st, need)
+    assert torch.equal(a, before)
+    buf = ws.get(lib.scoup_uplift_workspace_bytes(dg.n, C.byref(vs), need, vb))
+    st = lib.scoup_uplift_accumulate(C.byref(gs), C.byref(vs), a.data_ptr(), 1, need, vb, buf.data_ptr(),
+                                     buf.numel(), None, None)
+    torch.cuda.synchronize()
+    assert st == L.OK, lib.scoup_last_error()
+    f, r = full.cpu().numpy().astype(np.float64), a.cpu().numpy().astype(np.float64)
+    assert np.allclose(f, r, rtol=1e-5, atol=1e-12)
+    ref = OU.uplift_accumulate(sc.gaussians, sc.views)
+    PT.check_acc(r, ref.acc, ref.amb)
+
+
+@pytest.mark.parametrize("limit", [1, 64])
+def test_deferred_entry_overflow_adds_directly(limit):
+    """A per-view deferred-entry buffer capped far below what fragmented maps
+    need: the compositing adds the further regions' weights to the
+    accumulator itself; every kernel completes and the result still matches
+    the oracle (three levels, one of them cut into 1000 regions)."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    levels = [sg.make_views(800 + s, sc.views.cameras, s, 64, 4, hole_sites=1) for s in (8, 300, 1000)]
+    dg = P.gaussians_to_device(sc.gaussians)
+    try:
+        P.set_deferred_entry_limit(limit)
+        idxs, vals, accs, nc = P.uplift_levels(dg, [P.views_to_device(v) for v in levels], 4)
+        torch.cuda.synchronize()
+    finally:
+        P.set_deferred_entry_limit(0)
+    for lvl, v in enumerate(levels):
+        ref = OU.uplift_accumulate(sc.gaussians, v)
+        sa = PT.check_acc(accs[lvl].cpu().numpy(), ref.acc, ref.amb)
+        PT.check_topk(idxs[lvl].cpu().numpy(), vals[lvl].cpu().numpy(), ref.acc, ref.amb, 4)
+        assert abs(nc - ref.n_contrib) <= ref.count_slack
+        print(f"[entry limit {limit}, level {lvl}] acc={sa}")
+
+
+@pytest.mark.parametrize("m,kc", [(64, 5), (512, 16), (96, 3)])
+def test_code_widths_outside_the_pipelined_row_build(m, kc):
+    """Codes of K_code slots that are not a multiple of four or exceed eight
+    (the row build's scalar code loads), over codebooks of M atoms, full oracle."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    v = sg.make_views(600 + kc, sc.views.cameras, 40, m, kc, hole_sites=1)
+    _compare(sc.gaussians, v, kc, f"m{m}-kc{kc}")
+
+
+def test_large_workload_two_views_sampled_rows():
+    """The 3M-Gaussian workload (20x20x6 box, 1440x1080, 200 regions per view,
+    16-sparse codes over M=512, Top-16) on two of its views: 300 sampled rows
+    against the row-sampled oracle, every sampled row's Top-K checked."""
+    require_gpu()
+    sc = sg.make_scene("large", n_views=2)
+    assert sc.views.m_atoms == 512 and sc.views.k_code == 16 and sc.k_top == 16
+    idx, val, acc, nc = _run(sc.gaussians, sc.views, sc.k_top)
+    rows = np.random.default_rng(0).choice(sc.gaussians.n, 300, replace=False)
+    ref = OU.uplift_accumulate(sc.gaussians, sc.views, rows=rows)
+    sa = PT.check_acc(acc[rows], ref.acc, ref.amb)
+    st = PT.check_topk(idx[rows], val[rows], ref.acc, ref.amb, sc.k_top)
+    print(f"[large-2views] contrib={nc} acc={sa} topk={st}", flush=True)
+    assert (ref.acc.sum(1) > 0).sum() > 100
+
+
 def test_empty_and_invisible():
     require_gpu()
     sc = sg.make_scene("tiny")
