@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, packed FP32 not used
 STAGES = ["project", "pair_scan", "emit", "tile_sort", "composite", "topk",
           "render", "decode", "render_backward", "backward_gemm", "row_build", "relevancy", "relevancy_fold",
           "extra_apply"]
@@ -38,12 +37,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def flops_per_contribution(k_code: int) -> int:
-    """Algorithmic flops of one contribution: alpha (2 offsets, 6 for the
-    quadratic form, exp, opacity product, clamp = 11), compositing (1 - alpha,
-    T(1 - alpha), alpha T, cutoff test = 4) and Algorithm 1's inner loop
-    (k_code multiply-adds = 2 k_code)."""
-    return 15 + 2 * k_code
+FLOPS_PER_CONTRIBUTION = 14     # alpha (offsets 2, quadratic form 6, opacity product, clamp) +
+                                # compositing (1 - alpha, T (1 - alpha), alpha T, cutoff test); plus one exp
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector peak (256 CU x 2.4 GHz, packed FP32)
+
+
+def uplift_view_bytes(n, width, height, regions, k_code, touches):
+    """Algorithmic HBM bytes of one view of the uplift (Eq. 5 costs
+    O(|S_i| K) per Gaussian): read the Gaussians (44 B each), the view's
+    region map (4 B per pixel) and code table (8 B per code slot), and per
+    distinct (Gaussian, region) pair with weight one code's worth of
+    accumulator traffic (8 B per code slot)."""
+    return 44 * n + 4 * width * height + 8 * regions * k_code + 8 * k_code * touches
+
+
+def uplift_step_bytes(n, m, k, view_bytes):
+    """Whole uplift: the views plus zeroing the N x M accumulator, reading it
+    once for Top-K and writing N x K (index, value) pairs."""
+    return view_bytes + 4 * n * m + 4 * n * m + 8 * n * k
 
 
 def composite_source_hash():
@@ -74,15 +85,18 @@ def measured_traffic():
     return int(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(sc, rows=192):
-    """The FP64 oracle on a bounded sample: all Gaussians, view 0, a band of
-    ``rows`` image rows through the centre (projection + compositing +
-    accumulation), single process."""
+def _oracle_band(job):
+    """One worker of the CPU baseline: the FP64 oracle (projection +
+    compositing + accumulation) on rows [y0, y0 + rows) of one view of the
+    scene workload, all Gaussians.  Returns (contributions, seconds)."""
+    view, rows = job
     import numpy as np
+    import scenegen as sg
     from oracle import composite as OC
     from oracle import project as OP
     from oracle import uplift as OU
-    cam = sc.views.cameras[0]
+    sc = sg.make_scene("scene", n_views=view + 1)
+    cam = sc.views.cameras[view]
     y0 = max(0, cam.height // 2 - rows // 2)
     mask = np.zeros(cam.width * cam.height, bool)
     mask[y0 * cam.width:(y0 + rows) * cam.width] = True
@@ -90,13 +104,42 @@ def cpu_baseline(sc, rows=192):
     t0 = time.perf_counter()
     proj = OP.project(sc.gaussians, cam)
     vw = OC.composite_view(proj, cam.width, cam.height, pixel_mask=mask, track_marginal=False)
-    OU.accumulate_view(acc, None, vw, sc.views.region_maps[0], int(sc.views.region_base[0]),
+    OU.accumulate_view(acc, None, vw, sc.views.region_maps[view], int(sc.views.region_base[view]),
                        sc.views.code_idx, sc.views.code_val, None, sc.views.m_atoms)
-    dt = time.perf_counter() - t0
-    return dict(value=vw.n_contrib / dt, unit="contributions/s", cores=1, kind="oracle",
-                sample=f"view 0, rows {y0}..{y0 + rows - 1} of {cam.width}x{cam.height}, "
-                       f"all {sc.gaussians.n} Gaussians: {vw.n_contrib} contributions in {dt:.1f} s "
-                       f"(FP64 NumPy, one process)")
+    return vw.n_contrib, time.perf_counter() - t0
+
+
+def cpu_baseline(workload, rows=96):
+    """The FP64 oracle timed on the host: one process per core (spawned, so
+    nothing of the GPU process is inherited), each on a band of ``rows`` image
+    rows through the centre of a different view of the 1M-Gaussian scene
+    (views are additive); rate = all contributions / the slowest worker's
+    time.  Then the same band of view 0 alone in this process (one core)."""
+    import multiprocessing as mp
+    if workload != "scene":
+        return None
+    # one worker per core of this process's share, at most 16 (the host share
+    # of one GPU; each worker holds its own copy of the scene, about 1.5 GB)
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_band, [(v, rows) for v in range(cores)])
+    n_all = sum(c for c, _ in res)
+    t_all = max(t for _, t in res)
+    c1, t1 = _oracle_band((0, rows))
+    return dict(value=n_all / t_all, unit="contributions/s", cores=cores, kind="oracle",
+                cpu_model=model, value_1core=c1 / t1,
+                sample=f"{cores} processes, each the FP64 NumPy oracle (projection of all 1,000,000 Gaussians, "
+                       f"compositing and accumulation) on a {rows}-row band through the centre of one of views "
+                       f"0..{cores - 1} (1008x756): {n_all} contributions, slowest worker {t_all:.1f} s; "
+                       f"one core alone: {c1} contributions of view 0 in {t1:.1f} s")
 
 
 def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
@@ -375,9 +418,10 @@ def main():
     # per-stage kernel time with HIP events on the launch stream (one extra step,
     # one view at a time, so that every kernel's events time it alone)
     P.set_views_in_flight(1)
-    lib.scoup_stage_timing(1)
+    lib.scoup_stage_timing(1)          # also turns on the uplift's U_v count for this step
     step()
     P.set_views_in_flight(args.views_in_flight)
+    touch_stats = P.uplift_touch_stats()
     stages = {}
     for sid, name in enumerate(STAGES):
         tot, cnt = C.c_double(), C.c_int64()
@@ -388,17 +432,39 @@ def main():
     lib.scoup_stage_timing(0)
     log(f"stages: {json.dumps(stages)}")
 
-    # roofline of the dominant kernel (compositing + accumulation, one launch per view)
-    dom = max(stages, key=lambda s: stages[s]["total_ms"])
+    touch = touch_stats
+    if touch["views"] != sc.views.n_views or touch["lost"]:
+        log(f"touch statistics incomplete: {touch}")
+
+    # roofline of the dominant kernel: the compositing + accumulation kernel
+    # (one launch per view), HBM-bound by the algorithmic byte model
+    v = sc.views
+    u_v = touch["touches"] / max(1, touch["views"])
+    regions = int(v.region_base[-1]) / v.n_views
+    w0 = v.cameras[0]
+    view_bytes = [uplift_view_bytes(n, c.width, c.height, int(v.region_base[i + 1] - v.region_base[i]),
+                                    v.k_code, u_v) for i, c in enumerate(v.cameras)]
+    per_view = sum(view_bytes) / v.n_views
     comp = stages["composite"]
-    per_launch_flops = nc / sc.views.n_views * flops_per_contribution(sc.views.k_code)
-    achieved = per_launch_flops / (comp["avg_us"] * 1e-6) / 1e12
-    roofline = dict(kernel="composite", dominant_stage=dom, bound="alu",
-                    achieved=round(achieved, 3), peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 5),
-                    traffic=measured_traffic() if sc.views.n_views == 200 and args.workload == "scene" else None,
-                    per_launch=f"{nc / sc.views.n_views:.4g} contributions x "
-                               f"{flops_per_contribution(sc.views.k_code)} flops")
+    comp_s = comp["avg_us"] * 1e-6
+    achieved = per_view / comp_s / 1e9
+    step_bytes = uplift_step_bytes(n, m, k, sum(view_bytes))
+    step_gbs = step_bytes / (ms * 1e-3) / 1e9
+    alu = nc / v.n_views * FLOPS_PER_CONTRIBUTION / comp_s / 1e12
+    roofline = dict(
+        kernel="k_composite_blk", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+        frac=round(achieved / HBM_PEAK_GBS, 5),
+        traffic=measured_traffic() if v.n_views == 200 and args.workload == "scene" else None,
+        per_launch=f"one view: 44 N + 4 H W + 8 R_v K_code + 8 K_code U_v = {per_view / 1e6:.1f} MB "
+                   f"(U_v = {u_v:.0f} distinct (Gaussian, region) pairs with weight, counted on the device)",
+        avg_launch_us=comp["avg_us"],
+        step={"bytes": int(step_bytes), "achieved_gbs": round(step_gbs, 1),
+              "frac": round(step_gbs / HBM_PEAK_GBS, 5),
+              "model": "sum over views of the per-view bytes + 4 N M (zero) + 4 N M (Top-K read) + 8 N K"},
+        alu={"achieved_tflops": round(alu, 3), "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+             "frac": round(alu / FP32_VECTOR_PEAK_TFLOPS, 5),
+             "per_contribution": f"{FLOPS_PER_CONTRIBUTION} flops + 1 exp"},
+        dominant_stage=max(stages, key=lambda s_: stages[s_]["total_ms"]))
 
     if args.copy_calibration:
         copy_calibration(torch)
@@ -413,7 +479,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the CPU sample ...")
-        cpu = cpu_baseline(sc)
+        cpu = cpu_baseline(args.workload)
         log(f"cpu baseline: {cpu}")
 
     w = sc.views.cameras[0]

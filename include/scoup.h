@@ -297,6 +297,19 @@ scoup_status scoup_render_backward(const scoup_gaussians* g, const int32_t* topk
 void scoup_stage_timing(int32_t enable);
 int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
 
+/* Statistics of the uplift calls completed while stage timing was enabled
+ * (reset by scoup_stage_timing): the distinct (Gaussian, region) pairs of
+ * level 0 that received a nonzero weight, summed over views -- U_v of the
+ * byte model of Eq. 5's O(|S_i| K) cost, one code read per such pair.  Each
+ * view's per-(Gaussian, block, region) records and deferred entries are
+ * inserted into a hash set held in the view's sort buffer after the view is
+ * composited (one more pass per view, statistics only).
+ *   touches  pairs found;  lost  pairs the set could not place (0 unless it filled);
+ *   direct   further-region weights added straight to the accumulator past a
+ *            full entry buffer (not in touches; each names at most one pair);
+ *   views    views counted.  NULL pointers are skipped.                     */
+void scoup_uplift_touch_stats(uint64_t* touches, uint64_t* lost, uint64_t* direct, uint64_t* views);
+
 /* Views in flight in the uplift (scoup_uplift, scoup_uplift_accumulate,
  * scoup_uplift_levels): up to k views of a view batch are projected, binned
  * and composited at the same time, each with its own binning buffers, view i

@@ -12,6 +12,10 @@ by (value descending, atom index ascending), so exact ties go to the lower
 index; only strictly positive entries are kept; fewer than K of them are
 padded with (index -1, value 0); a row that is all zero is all padding.
 
+U_v (region_touches) is pinned by the brute force's per-pixel lists and by
+the closed forms of a one-region map (U_v = Gaussians that contribute) and
+a map with one region per pixel (U_v = contributions).
+
 Parity pinned by: the brute force (per-entry), the invariants row-sum = Z_i,
 linearity in the codes, additivity over views, one-hot codes giving per-region
 weight sums, a uniform code uplifting to itself, and Top-K against a full sort.
@@ -114,6 +118,25 @@ def uplift_accumulate(gaussians, views, rows: Optional[np.ndarray] = None,
         accumulate_view(acc, amb, vw, views.region_maps[v], int(views.region_base[v]),
                         views.code_idx, views.code_val, row_of, m, amb_list)
     return UpliftResult(acc, amb, ncon, slack, rows)
+
+
+def region_touches(gaussians, views, view_ids=None) -> np.ndarray:
+    """U_v per view: the distinct (Gaussian i, region r) pairs with a
+    contribution e_i(v,p) > 0 at some pixel p of region r >= 0, i.e. the
+    pairs whose region code Algorithm 1's inner loop adds at least once in
+    view v (the unit of Eq. 5's O(|S_i| K) cost once pixels of a region share
+    its code).  Returns int64 (number of views,)."""
+    cov = covariance3d(gaussians.log_scales, gaussians.quats)
+    vids = list(range(views.n_views)) if view_ids is None else list(view_ids)
+    out = np.zeros(len(vids), np.int64)
+    for k, v in enumerate(vids):
+        cam = views.cameras[v]
+        vw = composite_view(project(gaussians, cam, cov), cam.width, cam.height, track_marginal=False)
+        reg = views.region_maps[v].reshape(-1)[vw.pixel].astype(np.int64)
+        has = (reg >= 0) & (vw.e > 0)
+        nreg = int(views.region_base[v + 1] - views.region_base[v])
+        out[k] = np.unique(vw.gauss[has].astype(np.int64) * max(nreg, 1) + reg[has]).shape[0]
+    return out
 
 
 def topk_rows(acc: np.ndarray, k: int):

@@ -74,6 +74,8 @@ SIGNATURES = {
     "scoup_set_views_in_flight": (None, [C.c_int32]),
     "scoup_views_in_flight": (C.c_int32, []),
     "scoup_set_deferred_entry_limit": (None, [C.c_int64]),
+    "scoup_uplift_touch_stats": (None, [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint64)]),
     "scoup_last_error": (C.c_char_p, []),
     "scoup_version": (C.c_char_p, []),
 }

@@ -286,6 +286,21 @@ def views_in_flight() -> int:
     return int(L.load().scoup_views_in_flight())
 
 
+def stage_timing(enable: bool) -> None:
+    """Per-stage kernel timing (HIP events) and uplift statistics on or off
+    (turning either way resets the counters)."""
+    L.load().scoup_stage_timing(1 if enable else 0)
+
+
+def uplift_touch_stats() -> dict:
+    """Uplift statistics collected while stage timing is on: distinct
+    (Gaussian, region) pairs with weight summed over views (U_v), pairs the
+    counting set lost, direct further-region adds, views counted."""
+    vals = [C.c_uint64() for _ in range(4)]
+    L.load().scoup_uplift_touch_stats(*[C.byref(x) for x in vals])
+    return dict(zip(("touches", "lost", "direct", "views"), (int(x.value) for x in vals)))
+
+
 def set_deferred_entry_limit(n: int) -> None:
     """Cap the uplift's per-view buffer of deferred further-region entries at
     ``n`` entries (0 = the workspace's capacity); past it the compositing adds

@@ -116,6 +116,8 @@ int max_tiles_of(const scoup_views* v) {   // 8x8 blocks of the uplift
 // further sets of per-view binning buffers follow the first layout.
 constexpr int kLanes = 4;                     // workspace sized for this many; the setting below may use fewer
 int g_views_in_flight = kLanes;
+struct TouchStats { uint64_t touches = 0, lost = 0, direct = 0, views = 0; };
+TouchStats g_touch;                           // collected while stage timing is on
 unsigned int g_extra_cap_limit = 0;           // 0: the layout's deferred-entry capacity
 BinLayout uplift_layout(int64_t n, int mt, int64_t cap, int vb, int n_levels) {
   return bin_layout(n, mt, cap, vb, vb * n_levels, true);
@@ -298,6 +300,7 @@ extern "C" {
 
 void scoup_stage_timing(int32_t enable) {
   g_timer.on = enable != 0;
+  g_touch = TouchStats{};
   for (int i = 0; i < kNumStages; ++i) { g_timer.total_ms[i] = 0.0; g_timer.launches[i] = 0; }
 }
 
@@ -308,6 +311,13 @@ int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches) {
   return 0;
 }
 
+
+void scoup_uplift_touch_stats(uint64_t* touches, uint64_t* lost, uint64_t* direct, uint64_t* views) {
+  if (touches) *touches = g_touch.touches;
+  if (lost) *lost = g_touch.lost;
+  if (direct) *direct = g_touch.direct;
+  if (views) *views = g_touch.views;
+}
 
 void scoup_set_views_in_flight(int32_t k) { g_views_in_flight = std::max(1, std::min<int>(kLanes, k)); }
 
@@ -431,7 +441,9 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
   unsigned int* off_all = a[0].bin.offsets;
   float2* rec_all = reinterpret_cast<float2*>(base + L.records);
   const size_t rec_view = 2 * (size_t)pair_capacity;           // float2 per view and level
+  const bool stats = StageTimer::enabled();
   for (int k = 0; k < lanes; ++k) {
+    a[k].count_touches = stats ? 1 : 0;
     a[k].n_levels = n_levels;
     a[k].m_atoms = v->m_atoms;
     for (int l = 0; l < n_levels; ++l) {
@@ -510,6 +522,14 @@ scoup_status uplift_impl(const scoup_gaussians* g, int n_levels, const scoup_vie
     h.any_overflow |= hs[k].any_overflow;
     h.max_pairs = std::max(h.max_pairs, hs[k].max_pairs);
     h.data_error |= hs[k].data_error;
+  }
+  if (stats && g->n > 0) {
+    for (int k = 0; k < lanes; ++k) {
+      g_touch.touches += hs[k].touches;
+      g_touch.lost += hs[k].touch_lost;
+      g_touch.direct += hs[k].n_direct;
+    }
+    g_touch.views += (uint64_t)v->n_views;
   }
   if (h.any_overflow) {
     g_required_pairs = (int64_t)h.max_pairs;

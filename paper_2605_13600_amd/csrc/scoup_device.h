@@ -111,6 +111,9 @@ struct Status {
   unsigned int n_big;           // tiles of the current view sorted in global memory
   unsigned long long n_extra;   // deferred further-region entry slots reserved in the current view
   unsigned long long contrib;   // contributions composited
+  unsigned long long touches;   // statistics: distinct (Gaussian, region) pairs with weight, level 0
+  unsigned long long touch_lost;  // statistics: pairs the counting set could not place
+  unsigned long long n_direct;  // further-region weights added straight to the accumulator
 };
 
 struct CamDev {

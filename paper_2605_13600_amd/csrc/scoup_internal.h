@@ -90,6 +90,7 @@ struct UpliftViewArgs {
   LevelView lv[kMaxLevels];
   float4* extra;           // [extra_cap] deferred weights of regions beyond a block's two record
   unsigned int extra_cap;  //   regions: (Gaussian id, level, global region id as int bits, weight)
+  int count_touches;       // statistics: count the view's distinct (Gaussian, region) pairs (level 0)
 };
 hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s);
 

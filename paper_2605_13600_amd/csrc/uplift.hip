@@ -55,6 +55,7 @@ __device__ __forceinline__ void add_region_direct(const int* code_idx, const flo
                                                   const float* dense_F, int dense_d, float* acc, float* zsum,
                                                   unsigned int id, long long greg, float w, int m_atoms,
                                                   Status* st) {
+  atomicAdd(&st->n_direct, 1ull);
   if (dense_F) {
     const long long fr = greg * dense_d;
     const unsigned long long drow = (unsigned long long)id * (unsigned long long)dense_d;
@@ -817,6 +818,70 @@ __global__ __launch_bounds__(256) void k_apply_extra(UpliftViewArgs a, int m_ato
   }
 }
 
+// Statistics: U_v, the distinct (Gaussian, region) pairs of level 0 that
+// received a weight in the view, from its records (Gaussian of a record by a
+// binary search over the pair offsets) and its deferred entries, inserted
+// into an open-addressing set of 64-bit keys (Gaussian << 32 | region; a
+// mixing hash, linear probing, key + 1 so that 0 marks an empty slot).  New
+// keys are counted once per wave.
+__device__ __forceinline__ bool touch_insert(unsigned long long* table, unsigned long long cap,
+                                             unsigned long long key, Status* st) {
+  key += 1ull;
+  unsigned long long h = key;                  // 64-bit finaliser: every key bit reaches every hash bit
+  h ^= h >> 33; h *= 0xff51afd7ed558ccdull;
+  h ^= h >> 33; h *= 0xc4ceb9fe1a85ec53ull;
+  h ^= h >> 33;
+  h %= cap;
+  for (int probe = 0; probe < 256; ++probe) {
+    const unsigned long long prev = atomicCAS(&table[h], 0ull, key);
+    if (prev == 0ull) return true;
+    if (prev == key) return false;
+    h = h + 1 == cap ? 0ull : h + 1;
+  }
+  atomicAdd(&st->touch_lost, 1ull);
+  return false;
+}
+
+__global__ __launch_bounds__(256) void k_touch_clear(unsigned long long* table, unsigned long long cap,
+                                                     const Status* st) {
+  if (st->view_overflow) return;
+  for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < cap; i += gridDim.x * 256ull) table[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_touch_count(const float2* __restrict__ rec,
+                                                     const unsigned int* __restrict__ off, long long n,
+                                                     const float4* __restrict__ extra, unsigned int extra_cap,
+                                                     unsigned long long* table, unsigned long long cap, Status* st) {
+  if (st->view_overflow || n <= 0) return;
+  const unsigned long long nr = 2ull * st->total_pairs;
+  const unsigned long long total = nr + min(st->n_extra, (unsigned long long)extra_cap);
+  const int lane = threadIdx.x & 63;
+  for (unsigned long long t0 = blockIdx.x * 256ull; t0 < total; t0 += gridDim.x * 256ull) {
+    const unsigned long long t = t0 + threadIdx.x;
+    bool fresh = false;
+    if (t < nr) {
+      const float2 r = rec[t];
+      const int reg = __float_as_int(r.x);
+      if (r.y != 0.0f && reg >= 0) {
+        const unsigned int p = (unsigned int)(t >> 1);   // pair of the record
+        long long lo = 0, hi = n - 1;                     // last Gaussian whose pairs start at or before p
+        while (lo < hi) {
+          const long long mid = (lo + hi + 1) >> 1;
+          if (off[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        fresh = touch_insert(table, cap, ((unsigned long long)lo << 32) | (unsigned int)reg, st);
+      }
+    } else if (t < total) {
+      const float4 e = extra[t - nr];
+      if (e.w > 0.0f && __float_as_int(e.y) == 0)
+        fresh = touch_insert(table, cap, ((unsigned long long)__float_as_uint(e.x) << 32) |
+                                             (unsigned int)__float_as_int(e.z), st);
+    }
+    const unsigned long long m = __ballot(fresh);
+    if (lane == 0 && m) atomicAdd(&st->touches, (unsigned long long)__popcll(m));
+  }
+}
+
 hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
   hipError_t e = launch_bin_view(a.bin, s);
   if (e != hipSuccess) return e;
@@ -839,6 +904,14 @@ hipError_t launch_uplift_view(UpliftViewArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_apply_extra, dim3(std::min(2048u, (a.extra_cap + 255) / 256)), dim3(256), 0, s, a,
                        a.m_atoms, width, b.status);
     StageTimer::end(kStApplyExtra, s);
+  }
+  if (a.count_touches && b.n > 0) {          // the view's sort buffers are free once it is composited
+    unsigned long long* table = b.keys[b.sorted ^ 1];
+    const unsigned long long cap = (unsigned long long)b.capacity;
+    hipLaunchKernelGGL(k_touch_clear, dim3(1024), dim3(256), 0, s, table, cap, (const Status*)b.status);
+    hipLaunchKernelGGL(k_touch_count, dim3(2048), dim3(256), 0, s, (const float2*)a.lv[0].records,
+                       (const unsigned int*)b.offsets, b.n, (const float4*)a.extra, a.extra_cap, table, cap,
+                       b.status);
   }
   return hipGetLastError();
 }

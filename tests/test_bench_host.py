@@ -1,5 +1,5 @@
-"""Host-side logic of bench.py (no GPU): the multi-GPU refusal, the metric
-helpers and the committed counter summary it reads."""
+"""Host-side logic of bench.py (no GPU): the multi-GPU refusal, the byte
+model behind the roofline and the committed counter summary it reads."""
 import os
 import subprocess
 import sys
@@ -16,10 +16,16 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_flops_per_contribution():
-    # alpha (11) + compositing (4) + K_code multiply-adds
-    assert bench.flops_per_contribution(8) == 31
-    assert bench.flops_per_contribution(0) == 15
+def test_byte_model_of_the_uplift():
+    """Per view: Gaussians 44 B, region map 4 B per pixel, code table 8 B per
+    slot, 8 B per code slot per distinct (Gaussian, region) pair; per step
+    the accumulator is zeroed and read once (4 N M each) and N x K written."""
+    assert bench.uplift_view_bytes(10, 4, 3, 2, 8, 0) == 440 + 48 + 128
+    assert bench.uplift_view_bytes(0, 0, 0, 0, 8, 5) == 320
+    assert bench.uplift_step_bytes(10, 64, 4, 1000) == 1000 + 2 * 4 * 10 * 64 + 8 * 10 * 4
+    # the 1M-Gaussian scene at U_v = 0.8 M: about 98.6 MB per view
+    per_view = bench.uplift_view_bytes(1_000_000, 1008, 756, 120, 8, 800_000)
+    assert 97e6 < per_view < 100e6
 
 
 def test_counter_summary_is_parsed_and_tied_to_the_source():

@@ -215,6 +215,36 @@ def test_large_workload_two_views_sampled_rows():
     assert (ref.acc.sum(1) > 0).sum() > 100
 
 
+@pytest.mark.parametrize("sites,limit", [(8, 0), (300, 0), (300, 16)])
+def test_region_touch_count(sites, limit):
+    """U_v summed over views, counted on the device while statistics are on,
+    against the oracle's distinct (Gaussian, region) pairs with a contribution;
+    with a capped entry buffer the direct adds bound the rest."""
+    require_gpu()
+    sc = sg.make_scene("tiny", res=(70, 45))
+    v = sg.make_views(950 + sites, sc.views.cameras, sites, 64, 4, hole_sites=1)
+    dg, dv = to_device(sc.gaussians, v)
+    try:
+        P.set_deferred_entry_limit(limit)
+        P.stage_timing(True)
+        P.uplift(dg, dv, 4)
+        torch.cuda.synchronize()
+        st = P.uplift_touch_stats()
+    finally:
+        P.stage_timing(False)
+        P.set_deferred_entry_limit(0)
+    ref = OU.uplift_accumulate(sc.gaussians, v)
+    u_ref = int(OU.region_touches(sc.gaussians, v).sum())
+    print(f"[touches sites={sites} limit={limit}] gpu={st} oracle={u_ref} slack={ref.count_slack}")
+    assert st["views"] == v.n_views and st["lost"] == 0
+    if limit == 0:
+        assert st["direct"] == 0
+        assert abs(st["touches"] - u_ref) <= ref.count_slack
+    else:
+        assert st["direct"] > 0
+        assert st["touches"] - ref.count_slack <= u_ref <= st["touches"] + st["direct"] + ref.count_slack
+
+
 def test_empty_and_invisible():
     require_gpu()
     sc = sg.make_scene("tiny")

@@ -122,6 +122,30 @@ def test_brute_force_tiny_workload_subset():
     assert res.n_contrib > 1000
 
 
+@pytest.mark.parametrize("seed", [3, 4])
+def test_region_touches_brute_force_and_closed_forms(seed):
+    g, views = S.small_scene(seed, n=60, holes=1)
+    got = OU.region_touches(g, views)
+    for v, cam in enumerate(views.cameras):
+        rmap = views.region_maps[v]
+        pairs = set()
+        for (px, py), (lst, _) in BR.pixel_weights(g, cam).items():
+            r = int(rmap[py, px])
+            if r >= 0:
+                pairs.update((i, r) for i, e in lst if e > 0)
+        assert got[v] == len(pairs)
+    cam = views.cameras[0]
+    vw = _weights(g, cam)
+    one = sg.Views([cam], [np.zeros((cam.height, cam.width), np.int32)], np.array([0, 1], np.int64),
+                   views.code_idx[:1], views.code_val[:1], views.m_atoms)
+    assert OU.region_touches(g, one)[0] == np.unique(vw.gauss[vw.e > 0]).shape[0]
+    per = np.arange(cam.width * cam.height, dtype=np.int32).reshape(cam.height, cam.width)
+    codes_i = np.zeros((per.size, views.code_idx.shape[1]), np.int32)
+    codes_v = np.zeros((per.size, views.code_idx.shape[1]), np.float32)
+    each = sg.Views([cam], [per], np.array([0, per.size], np.int64), codes_i, codes_v, views.m_atoms)
+    assert OU.region_touches(g, each)[0] == int((vw.e > 0).sum())
+
+
 # ---------------------------------------------------------------- invariants
 def test_weights_sum_to_one_minus_transmittance():
     sc = sg.make_scene("tiny")
