@@ -227,6 +227,23 @@ scoup_status scoup_decode(const void* coeff, scoup_dtype in_dtype, float coeff_s
                           int32_t m_atoms, const float* codebook, int32_t dim, void* features,
                           scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream);
 
+/* scoup_decode for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation, arguments, kernels and results as scoup_decode, without
+ * a workspace.  The converted codebook and its scale live in a fixed scratch
+ * array of scoup_decode_noalloc_max_bytes() bytes (8 MiB) that the library
+ * holds on each GPU it runs on until the process ends; codebooks whose
+ * scoup_decode_workspace_bytes exceed it are rejected with SCOUP_E_ARG
+ * (e.g. F32 up to m_atoms * dim of about 2M).  The call allocates nothing and
+ * records no stage timing.  Every call on a GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (other threads, other streams) race and must
+ * be serialised by the caller.  Returns after the work is complete, like
+ * scoup_decode.                                                             */
+size_t scoup_decode_noalloc_max_bytes(void);
+scoup_status scoup_decode_noalloc(const void* coeff, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                                  int32_t m_atoms, const float* codebook, int32_t dim, void* features,
+                                  scoup_dtype out_dtype, void* stream);
+
 /* Workspace bytes for scoup_relevancy (the codebook folded into the query
  * and canonical vectors, in MFMA operand order).                            */
 size_t scoup_relevancy_workspace_bytes(int32_t m_atoms, int32_t n_queries, scoup_dtype in_dtype);

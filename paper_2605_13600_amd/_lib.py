@@ -60,6 +60,9 @@ SIGNATURES = {
     "scoup_decode_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int]),
     "scoup_decode": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_int32, C.c_void_p, C.c_int32,
                                C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "scoup_decode_noalloc_max_bytes": (C.c_size_t, []),
+    "scoup_decode_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_int32, C.c_void_p,
+                                       C.c_int32, C.c_void_p, C.c_int, C.c_void_p]),
     "scoup_relevancy_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int]),
     "scoup_relevancy": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_int32, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_float, C.c_void_p,

@@ -14,6 +14,13 @@
 
 using namespace scoup;
 
+// Scratch of scoup_decode_noalloc: one array per GPU the library runs on,
+// held until the process ends.  In host code the array's name is not a
+// device address: the per-device address comes from hipGetSymbolAddress,
+// taken once per device (with that device current) on the first call there.
+constexpr size_t kDecodeScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kDecodeScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -268,13 +275,13 @@ hipEvent_t take_event() {
 namespace scoup {
 bool StageTimer::enabled() { return g_timer.on; }
 void StageTimer::begin(int stage, hipStream_t s) {
-  if (!g_timer.on) return;
+  if (!g_timer.on || stage < 0) return;
   hipEvent_t e = take_event();
   if (e) hipEventRecord(e, s);
   g_timer.open[stage] = e;
 }
 void StageTimer::end(int stage, hipStream_t s) {
-  if (!g_timer.on) return;
+  if (!g_timer.on || stage < 0) return;
   hipEvent_t b = g_timer.open[stage];
   g_timer.open[stage] = nullptr;
   hipEvent_t e = take_event();
@@ -758,10 +765,11 @@ size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in
   return 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));
 }
 
-scoup_status scoup_decode(const void* coeff_map, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
-                          int32_t m_atoms, const float* codebook, int32_t dim, void* features,
-                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream) {
-  g_err.clear();
+namespace {
+// Eq. 8 with the converted codebook and its scale in `ws`; `stage` < 0 records no timing events.
+scoup_status decode_impl(const void* coeff_map, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                         int32_t m_atoms, const float* codebook, int32_t dim, void* features, scoup_dtype out_dtype,
+                         void* ws, size_t ws_bytes, void* stream, int stage) {
   if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3)
     return fail(SCOUP_E_ARG, "unknown input dtype");
   if (out_dtype != SCOUP_F32 && out_dtype != SCOUP_BF16) return fail(SCOUP_E_ARG, "output dtype must be F32 or BF16");
@@ -785,10 +793,57 @@ scoup_status scoup_decode(const void* coeff_map, scoup_dtype in_dtype, float coe
   a.cb_scale = in_dtype == SCOUP_FP8_E4M3 ? scale : nullptr;
   a.out_mul = 1.0f / coeff_scale;
   a.out = features;
-  HIP_TRY(launch_decode(a, s));
+  HIP_TRY(launch_decode(a, s, stage));
   HIP_TRY(hipStreamSynchronize(s));
-  StageTimer::collect();
+  if (stage >= 0) StageTimer::collect();
   return SCOUP_OK;
+}
+
+// the address of this GPU's copy of `scratch` (below the namespace)
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+hipError_t decode_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+scoup_status scoup_decode(const void* coeff_map, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                          int32_t m_atoms, const float* codebook, int32_t dim, void* features,
+                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  return decode_impl(coeff_map, in_dtype, coeff_scale, n_pixels, m_atoms, codebook, dim, features, out_dtype, ws,
+                     ws_bytes, stream, kStDecode);
+}
+
+size_t scoup_decode_noalloc_max_bytes(void) { return kDecodeScratchBytes; }
+
+scoup_status scoup_decode_noalloc(const void* coeff_map, scoup_dtype in_dtype, float coeff_scale, int64_t n_pixels,
+                                  int32_t m_atoms, const float* codebook, int32_t dim, void* features,
+                                  scoup_dtype out_dtype, void* stream) {
+  g_err.clear();
+  if (m_atoms >= 1 && dim >= 1 &&
+      scoup_decode_workspace_bytes(m_atoms, dim, in_dtype) > kDecodeScratchBytes)
+    return fail(SCOUP_E_ARG, "codebook of " + std::to_string(m_atoms) + " x " + std::to_string(dim) +
+                                 " needs more than the " + std::to_string(kDecodeScratchBytes) +
+                                 " bytes of scratch of scoup_decode_noalloc; use scoup_decode");
+  void* ws = nullptr;
+  HIP_TRY(decode_scratch(&ws));
+  return decode_impl(coeff_map, in_dtype, coeff_scale, n_pixels, m_atoms, codebook, dim, features, out_dtype, ws,
+                     kDecodeScratchBytes, stream, -1);
 }
 
 size_t scoup_relevancy_workspace_bytes(int32_t m_atoms, int32_t n_queries, scoup_dtype in_dtype) {

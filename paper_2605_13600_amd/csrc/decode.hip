@@ -109,6 +109,8 @@ __device__ __forceinline__ float fp8_scale_from(unsigned int maxbits) {
   return mx > 0.0f ? exp2f(floorf(log2f(448.0f / mx))) : 1.0f;
 }
 
+__global__ void k_clear_u32(unsigned int* p) { *p = 0u; }
+
 __global__ void k_fp8_scale(const unsigned int* __restrict__ maxbits, float* scale) {
   scale[0] = fp8_scale_from(*maxbits);
 }
@@ -387,8 +389,7 @@ hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void
   const int grid = (int)((total + 255) / 256);
   if (in_dtype == SCOUP_FP8_E4M3) {
     unsigned int* maxbits = reinterpret_cast<unsigned int*>(scale + 1);
-    const hipError_t e = hipMemsetAsync(maxbits, 0, sizeof(unsigned int), s);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(1), 0, s, maxbits);   // a kernel, not a memset node
     const long long n = (long long)m * d;
     const int gb = (int)std::min<long long>(256, (n + 255) / 256);
     hipLaunchKernelGGL(k_absmax, dim3(gb), dim3(256), 0, s, C, n, maxbits);
