@@ -196,6 +196,37 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
             "decode_mfma_ceiling": round(min(1.0, (flops / bytes_) / (pk * 1e12 / (HBM_PEAK_GBS * 1e9))), 4),
             "contributions_per_view": nc,
         }
+        # the one-pass render (Eq. 7 + Eq. 8 fused, coefficient rows kept on chip)
+        Ff, _, _, _ = P.render(dg, dti, dtv, dC, cams[0], in_dtype=dt, out_dtype=out_dt, want_t_final=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for cam in cams:
+            Ff, _, _, _ = P.render(dg, dti, dtv, dC, cam, in_dtype=dt, out_dtype=out_dt, want_t_final=False)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        lib.scoup_stage_timing(1)
+        for cam in cams[:min(5, n_views)]:
+            P.render(dg, dti, dtv, dC, cam, in_dtype=dt, out_dtype=out_dt, want_t_final=False)
+        lib.scoup_stage_stats(6, C_byref(tot), C_byref(cnt))
+        fk_us = tot.value * 1e3 / max(1, cnt.value)
+        lib.scoup_stage_timing(1)
+        for cam in cams[:min(5, n_views)]:
+            P.render_coeff(dg, dti, dtv, cam, m, dtype=dt, want_t_final=False)
+        lib.scoup_stage_stats(6, C_byref(tot), C_byref(cnt))
+        map_us = tot.value * 1e3 / max(1, cnt.value)
+        lib.scoup_stage_timing(0)
+        res[dt]["map_kernel_avg_us"] = round(map_us, 1)
+        res[dt]["map_kernel_hbm_frac"] = round((gaussians.n * (48 + 8 * k) + px * m * in_b[dt]) /
+                                               (map_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        # algorithmic bytes of the fused kernel: splats + code slots read per Gaussian
+        # (48 + 8 K), the feature rows written
+        f_bytes = gaussians.n * (48 + 8 * k) + px * d * (4 if out_dt == "f32" else 2)
+        res[dt].update({
+            "fused_render_mpix_s": round(px * n_views / t_f / 1e6, 2),
+            "fused_kernel_avg_us": round(fk_us, 1),
+            "fused_kernel_hbm_frac": round(f_bytes / (fk_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "fused_kernel_tflops": round(2.0 * px * m * d / (fk_us * 1e-6) / 1e12, 1),
+        })
         # query path: render + fused decode/relevancy (App. B), 16 queries, 4 canonical vectors
         R = P.relevancy(W, dC, dQ, dCanon, dt, coeff_scale=scl)
         torch.cuda.synchronize()

@@ -195,7 +195,8 @@ size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam
 /* Eq. 7 for one camera: coeff_map[p*m + j] = coeff_scale * sum over Gaussians i
  * in N_{v,p} (same compositing as the uplift) of e_i(v,p) * topk_val[i*k + s]
  * for every slot s with topk_idx[i*k + s] == j (slots with index -1 are
- * skipped).  Accumulation is float32; the map is written once per pixel in
+ * skipped).  Accumulation is float32, each map entry summed in the pixel's
+ * front-to-back order (bit-reproducible); the map is written once per pixel in
  * coeff_dtype (F32, BF16 round-to-nearest-even, or FP8 E4M3 saturating; use
  * coeff_scale to place FP8 values in range, e.g. 256 since coefficients are
  * at most 1).
@@ -210,6 +211,40 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
                                 const scoup_camera* cam, void* coeff_map, scoup_dtype coeff_dtype,
                                 float coeff_scale, float* t_final, void* ws, size_t ws_bytes,
                                 unsigned long long* n_contrib, void* stream);
+
+/* Workspace bytes for scoup_render: the codebook converted to in_dtype in
+ * MFMA operand order, then scoup_render_workspace_bytes(n, cam, pair_capacity)
+ * (0 picks 8 pairs per Gaussian).                                           */
+size_t scoup_render_decode_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t m_atoms,
+                                           int32_t dim, scoup_dtype in_dtype, int64_t pair_capacity);
+
+/* The render of Sec. 4.3 in one pass: Eq. 7 and then Eq. 8 for one camera,
+ *   features[p*dim + d] = sum_j W_hat(p)[j] codebook[j*dim + d]
+ * with W_hat(p) the float32 coefficient row of scoup_render_coeff, kept on
+ * chip per 8x8 pixel block and multiplied by the codebook on MFMA (float32
+ * accumulation) before the next block: the P x m map never reaches memory
+ * unless coeff_map asks for it.  in_dtype is the precision of that product:
+ * F32; BF16 (rows and codebook rounded to nearest even); FP8 E4M3 (rows times
+ * 256, codebook times a power-of-two scale, both divided out in float32).
+ * The features equal scoup_decode applied to the scoup_render_coeff map of
+ * the same precision (F32 map, BF16 map, FP8 map with coeff_scale 256), bit
+ * for bit.  Pixels without a contribution get zero features.
+ *   topk_idx/val   device [n*k], 1 <= k <= 16, indices < m_atoms (else SCOUP_E_DATA)
+ *   codebook       device float32 [m_atoms*dim], 1 <= m_atoms <= 512, 1 <= dim <= 1024
+ *   coeff_map      device float32 [H*W*m_atoms] (the float32 W_hat, as for the
+ *                  backward), or NULL
+ *   t_final        device float32 [H*W] transmittance left at each pixel, or NULL
+ *   features       device [H*W*dim] of out_dtype (F32 or BF16, round to nearest even)
+ *   ws, ws_bytes   at least scoup_render_decode_workspace_bytes(...); the pair
+ *                  capacity is what remains after the converted codebook
+ *   n_contrib      device uint64 [1] (+=) contributions composited, or NULL
+ * Returns SCOUP_E_WORKSPACE when the view has more (Gaussian, block) pairs
+ * than the workspace holds (scoup_required_pair_capacity() gives the count). */
+scoup_status scoup_render(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val, int32_t k,
+                          const scoup_camera* cam, const float* codebook, int32_t m_atoms, int32_t dim,
+                          scoup_dtype in_dtype, float* coeff_map, float* t_final, void* features,
+                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, unsigned long long* n_contrib,
+                          void* stream);
 
 /* Workspace bytes for scoup_decode (the codebook converted to in_dtype and
  * arranged in MFMA operand order).                                          */

@@ -363,6 +363,43 @@ def render_coeff(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Ten
     raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
 
 
+def render(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, codebook: torch.Tensor, cam,
+           in_dtype: str = "bf16", out_dtype: str = "bf16", want_coeff: bool = False, want_t_final: bool = True,
+           stream=None, workspace: Optional[Workspace] = None, pair_capacity: int = 0):
+    """Sec. 4.3 render in one pass (Eq. 7 then Eq. 8): per-pixel features
+    (H, W, D) in ``out_dtype`` decoded on MFMA in ``in_dtype`` from the float32
+    coefficient rows, which stay on chip.  Returns (features, coeff (H, W, M)
+    float32 or None, t_final (H, W) or None, n_contrib)."""
+    lib = L.load()
+    dev = g.means.device
+    c = camera_struct(cam)
+    H, W = int(cam.height), int(cam.width)
+    m, d = codebook.shape
+    k = int(topk_idx.shape[1])
+    feat = torch.empty((H, W, d), dtype=_TORCH_DT[out_dtype], device=dev)
+    coeff = torch.empty((H, W, m), dtype=torch.float32, device=dev) if want_coeff else None
+    tf = torch.empty((H, W), dtype=torch.float32, device=dev) if want_t_final else None
+    ws = workspace or _workspace(dev)
+    gs = g.struct()
+    key = ("render", g.n, W, H)
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        nbytes = lib.scoup_render_decode_workspace_bytes(g.n, C.byref(c), m, d, _DT[in_dtype], cap)
+        buf = ws.get(nbytes)
+        cnt.zero_()
+        st = lib.scoup_render(C.byref(gs), _ptr(topk_idx), _ptr(topk_val), k, C.byref(c), _ptr(codebook), m, d,
+                              _DT[in_dtype], _ptr(coeff), _ptr(tf), _ptr(feat), _DT[out_dtype], _ptr(buf),
+                              buf.numel(), _ptr(cnt), _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return feat, coeff, tf, int(cnt.item())
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
 def decode(coeff: torch.Tensor, codebook: torch.Tensor, in_dtype: str = "bf16", coeff_scale: float = 1.0,
            out_dtype: str = "bf16", stream=None, workspace: Optional[Workspace] = None) -> torch.Tensor:
     """Eq. 8: features = coeff @ codebook on MFMA.  ``coeff`` is (..., M) in
@@ -442,9 +479,8 @@ class RenderDecode(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, topk_val, codebook, g, topk_idx, cam):
-        m = int(codebook.shape[0])
-        W, tf, _, _ = render_coeff(g, topk_idx, topk_val, cam, m, dtype="f32")
-        F = decode(W, codebook, "f32", out_dtype="f32")
+        F, W, tf, _ = render(g, topk_idx, topk_val, codebook, cam, in_dtype="f32", out_dtype="f32",
+                             want_coeff=True)
         ctx.save_for_backward(topk_val, codebook, topk_idx, W)
         ctx.g, ctx.cam = g, cam
         ctx.mark_non_differentiable(tf)

@@ -708,27 +708,30 @@ size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam
   return bin_layout(n_gaussians, tiles_of(cam->width, cam->height, 3), pair_capacity, 1, 0, false).total;
 }
 
-scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
-                                int32_t k, int32_t m_atoms, const scoup_camera* cam, void* coeff_map,
-                                scoup_dtype coeff_dtype, float coeff_scale, float* t_final, void* ws,
-                                size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
-  g_err.clear();
+namespace {
+// Render (and decode) of one camera; map / features / t_final optional; `prep`
+// holds the converted codebook (NULL: no decode).
+scoup_status render_impl(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val, int32_t k,
+                         int32_t m_atoms, const scoup_camera* cam, void* coeff_map, scoup_dtype coeff_dtype,
+                         float coeff_scale, float* t_final, const float* codebook, int32_t dim,
+                         scoup_dtype in_dtype, void* features, scoup_dtype out_dtype, void* ws, size_t ws_bytes,
+                         unsigned long long* n_contrib, void* stream) {
   scoup_status st = check_gaussians(g);
   if (st != SCOUP_OK) return st;
   if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
   if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
   if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
   if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
-  if (coeff_dtype != SCOUP_F32 && coeff_dtype != SCOUP_BF16 && coeff_dtype != SCOUP_FP8_E4M3)
-    return fail(SCOUP_E_ARG, "unknown coefficient dtype");
-  if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
-  if (!coeff_map) return fail(SCOUP_E_ARG, "coeff_map is NULL");
   if (g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  const bool decode = codebook != nullptr;
+  size_t pre = 0;
+  if (decode) pre = 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));
+  if (ws_bytes <= pre) return fail(SCOUP_E_WORKSPACE, "workspace smaller than the converted codebook");
   HIP_TRY(ensure_lds_limits());
   const int shift = 3;
   const int mt = tiles_of(cam->width, cam->height, shift);
-  const long long capacity = capacity_for(g->n, mt, ws_bytes);
+  const long long capacity = capacity_for(g->n, mt, ws_bytes - pre);
   if (capacity < 1) {
     g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
     return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
@@ -736,16 +739,30 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0, false);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  RenderViewArgs a{};
-  fill_bin(a.bin, g, base, L, capacity, shift, kSortCap);
+  RenderBlockArgs a{};
+  fill_bin(a.bin, g, base + pre, L, capacity, shift, kSortCap);
   a.bin.cam = to_dev(*cam);
   a.bin.tiles_x = (cam->width + 7) / 8;
   a.bin.n_tiles = mt;
   a.topk_idx = topk_idx; a.topk_val = topk_val; a.k = k; a.m_atoms = m_atoms;
-  a.out_dtype = coeff_dtype; a.out = coeff_map; a.out_scale = coeff_scale; a.t_final = t_final;
+  a.map = coeff_map; a.map_dtype = coeff_dtype; a.map_scale = coeff_scale; a.t_final = t_final;
+  a.in_dtype = -1;
+  a.out_dtype = out_dtype;
+  if (decode) {
+    float* scale = reinterpret_cast<float*>(base);
+    void* prep = base + 256;
+    HIP_TRY(launch_prep_codebook(codebook, m_atoms, dim, in_dtype, prep, scale, s, 0));
+    a.in_dtype = in_dtype;
+    a.codebook_prep = prep;
+    a.cb_scale = in_dtype == SCOUP_FP8_E4M3 ? scale : nullptr;
+    a.d = dim; a.kpad = decode_kpad(m_atoms, in_dtype); a.npad = decode_npad(dim);
+    a.q_scale = in_dtype == SCOUP_FP8_E4M3 ? 256.0f : 1.0f;
+    a.out_mul = 1.0f / a.q_scale;
+    a.features = features;
+  }
   Status* status = a.bin.status;
   HIP_TRY(hipMemsetAsync(status, 0, sizeof(Status), s));
-  HIP_TRY(launch_render_view(a, s));
+  HIP_TRY(launch_render_block(a, s, kStRender));
   if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, status, s));
   Status h{};
   HIP_TRY(hipMemcpyAsync(&h, status, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -758,6 +775,43 @@ scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_id
   }
   if (h.data_error & 4u) return fail(SCOUP_E_DATA, "a Top-K atom index is >= m_atoms");
   return SCOUP_OK;
+}
+}  // namespace
+
+scoup_status scoup_render_coeff(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val,
+                                int32_t k, int32_t m_atoms, const scoup_camera* cam, void* coeff_map,
+                                scoup_dtype coeff_dtype, float coeff_scale, float* t_final, void* ws,
+                                size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  if (coeff_dtype != SCOUP_F32 && coeff_dtype != SCOUP_BF16 && coeff_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown coefficient dtype");
+  if (!(coeff_scale > 0.f) || !std::isfinite(coeff_scale)) return fail(SCOUP_E_ARG, "coeff_scale must be > 0");
+  if (!coeff_map) return fail(SCOUP_E_ARG, "coeff_map is NULL");
+  return render_impl(g, topk_idx, topk_val, k, m_atoms, cam, coeff_map, coeff_dtype, coeff_scale, t_final, nullptr,
+                     0, SCOUP_F32, nullptr, SCOUP_F32, ws, ws_bytes, n_contrib, stream);
+}
+
+size_t scoup_render_decode_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t m_atoms,
+                                           int32_t dim, scoup_dtype in_dtype, int64_t pair_capacity) {
+  if (!cam || m_atoms < 1 || dim < 1) return 0;
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3) return 0;
+  const size_t r = scoup_render_workspace_bytes(n_gaussians, cam, pair_capacity);
+  return r ? 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype)) + r : 0;
+}
+
+scoup_status scoup_render(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val, int32_t k,
+                          const scoup_camera* cam, const float* codebook, int32_t m_atoms, int32_t dim,
+                          scoup_dtype in_dtype, float* coeff_map, float* t_final, void* features,
+                          scoup_dtype out_dtype, void* ws, size_t ws_bytes, unsigned long long* n_contrib,
+                          void* stream) {
+  g_err.clear();
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown decode dtype");
+  if (out_dtype != SCOUP_F32 && out_dtype != SCOUP_BF16) return fail(SCOUP_E_ARG, "output dtype must be F32 or BF16");
+  if (dim < 1 || dim > 1024) return fail(SCOUP_E_UNSUPPORTED, "dim must be in [1, 1024]");
+  if (!codebook || !features) return fail(SCOUP_E_ARG, "codebook or features is NULL");
+  return render_impl(g, topk_idx, topk_val, k, m_atoms, cam, coeff_map, SCOUP_F32, 1.0f, t_final, codebook, dim,
+                     in_dtype, features, out_dtype, ws, ws_bytes, n_contrib, stream);
 }
 
 size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in_dtype) {

@@ -114,17 +114,28 @@ struct RowBuildArgs {
 };
 hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s);
 
-struct RenderViewArgs {
+// Render of one camera (Eq. 7), optionally fused with the decode (Eq. 8):
+// binning, then one workgroup per 8x8 block.
+struct RenderBlockArgs {
   BinArgs bin;
-  const int* topk_idx;
+  const int* topk_idx;     // [n x k]
   const float* topk_val;
   int k, m_atoms;
-  int out_dtype;           // scoup_dtype of the coefficient map
-  void* out;
-  float out_scale;
-  float* t_final;
+  void* map;               // coefficient map [P x m] of map_dtype (times map_scale), or NULL
+  int map_dtype;
+  float map_scale;
+  float* t_final;          // [P] or NULL
+  int in_dtype;            // decode precision (scoup_dtype), or -1: no decode
+  int out_dtype;           // features F32 / BF16
+  const void* codebook_prep;   // launch_prep_codebook layout (kpad x npad)
+  const float* cb_scale;   // FP8 codebook scale (device), else NULL
+  int d, kpad, npad;
+  float q_scale;           // FP8: coefficients are converted times this
+  float out_mul;           // 1 / q_scale (FP8) or 1
+  void* features;          // [P x d] of out_dtype
 };
-hipError_t launch_render_view(RenderViewArgs& a, hipStream_t s);
+hipError_t launch_render_block(RenderBlockArgs& a, hipStream_t s, int stage);
+size_t render_block_lds_bytes(int m, int npad, int out_dtype);
 hipError_t render_set_lds_limits();
 
 struct DecodeArgs {

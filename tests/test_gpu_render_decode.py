@@ -137,3 +137,80 @@ def test_render_decode_end_to_end_scene_rows():
     assert stats["f32"][0] <= 1e-5
     assert stats["bf16"][0] <= 2e-2
     assert stats["fp8"][0] <= 2e-2
+
+
+@pytest.mark.parametrize("res,m,k,d", [((203, 77), 256, 8, 512), ((70, 45), 100, 5, 200), ((64, 48), 512, 16, 1024),
+                                       ((33, 17), 64, 4, 128)])
+def test_fused_render_equals_render_then_decode(res, m, k, d):
+    """scoup_render (Eq. 7 then Eq. 8 in one kernel, rows kept on chip) against
+    scoup_decode of the scoup_render_coeff map of the same precision.  With the
+    float32 map requested (the backward's path) the rows are summed exactly as
+    for the map: features, map and final transmittance bit for bit, in F32,
+    BF16 and FP8.  Without it, BF16 / FP8 rows are accumulated on MFMA from
+    bfloat16 products: cosine error against the same reference <= 1e-4 (BF16:
+    a bfloat16 rounding of each term) or 1e-2 (FP8), inside the 2e-2 bar, and
+    a second call gives the same bits."""
+    require_gpu()
+    g, cams, ti, tv = _render_scene(n=8_000, res=res, m=m, k=k)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    Ct = torch.from_numpy(sg.random_codebook(5, m, d)).cuda()
+    cam = cams[0]
+    W32, tf_ref, nc_ref, _ = P.render_coeff(dg, dti, dtv, cam, m, dtype="f32")
+    for dt in ("f32", "bf16", "fp8"):
+        for out in ("f32", "bf16"):
+            F, Wf, tf, nc = P.render(dg, dti, dtv, Ct, cam, in_dtype=dt, out_dtype=out, want_coeff=True)
+            F2, _, _, _ = P.render(dg, dti, dtv, Ct, cam, in_dtype=dt, out_dtype=out)
+            Wm, _, _, scl = P.render_coeff(dg, dti, dtv, cam, m, dtype=dt)
+            Fref = P.decode(Wm, Ct, dt, coeff_scale=scl, out_dtype=out)
+            torch.cuda.synchronize()
+            iv = (lambda t: t.view(torch.int16)) if out == "bf16" else (lambda t: t.view(torch.int32))
+            assert torch.equal(iv(F), iv(Fref)), (dt, out, float((F.float() - Fref.float()).abs().max()))
+            F3, _, _, _ = P.render(dg, dti, dtv, Ct, cam, in_dtype=dt, out_dtype=out)
+            torch.cuda.synchronize()
+            assert torch.equal(iv(F2), iv(F3)), (dt, out)
+            if dt == "f32":
+                assert torch.equal(iv(F), iv(F2)), (dt, out)
+            else:
+                a_ = F2.reshape(-1, d).double().cpu().numpy()
+                b_ = Fref.reshape(-1, d).double().cpu().numpy()
+                nz = np.linalg.norm(b_, axis=1) > 0
+                assert (np.abs(a_[~nz]) == 0).all()
+                e = _cos_err(a_[nz], b_[nz])
+                # BF16: one bfloat16 rounding per term; FP8: the rows' E4M3 rounding may land
+                # on the neighbouring code (3 mantissa bits) for entries that moved by it
+                assert e.max() <= (1e-4 if dt == "bf16" else 1e-2), (dt, out, float(e.max()))
+            assert torch.equal(Wf.view(torch.int32), W32.view(torch.int32))
+            assert torch.equal(tf, tf_ref) and nc == nc_ref
+    print(f"[fused render {res} M={m} K={k} D={d}] contrib={nc_ref}: features equal render + decode")
+
+
+def test_fused_render_full_view_against_oracle():
+    """The 1M-Gaussian scene's Gaussians, synthetic Top-8 over M=256, codebook
+    256x512, one 1440x1080 view rendered and decoded in one pass; 3000 sampled
+    pixels against the FP64 oracle: cosine error <= 1e-5 (FP32), <= 2e-2
+    (BF16, FP8)."""
+    require_gpu()
+    sc = sg.make_scene("scene", n_views=1)
+    g = sc.gaussians
+    cam = sg.orbit_cameras(78, 100, 12.0, 1.0, 4.0, 1.0, 0.5, 1440, 1080, 60.0)[0]
+    ti, tv = sg.random_topk(13, g.n, 256, 8)
+    C = sg.random_codebook(14, 256, 512)
+    dg = P.gaussians_to_device(g)
+    dti, dtv, Ct = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda(), torch.from_numpy(C).cuda()
+    pix = np.random.default_rng(1).choice(1440 * 1080, 3000, replace=False)
+    mask = np.zeros(1440 * 1080, bool); mask[pix] = True
+    rr = OR.render_coeff(g, ti, tv, cam, 256, pixel_mask=mask)
+    Fref = OR.decode(rr.coeff, C)
+    cov = rr.t_final < 1.0
+    stats = {}
+    for dt in ("f32", "bf16", "fp8"):
+        F, _, tf, nc = P.render(dg, dti, dtv, Ct, cam, in_dtype=dt, out_dtype="f32" if dt == "f32" else "bf16")
+        Fs = F.reshape(-1, 512)[torch.from_numpy(rr.pixels).cuda()].float().cpu().numpy()
+        e = _cos_err(Fs, Fref, cov)
+        stats[dt] = (float(e.max()), float(np.percentile(e, 99)), float(e.mean()))
+        assert np.abs(Fs[~cov]).max() == 0 if (~cov).any() else True
+    print(f"[fused render 1440x1080] contrib={nc} covered={int(cov.sum())} cos err (max,p99,mean) {stats}")
+    assert stats["f32"][0] <= 1e-5
+    assert stats["bf16"][0] <= 2e-2
+    assert stats["fp8"][0] <= 2e-2
