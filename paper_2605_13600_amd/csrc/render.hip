@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
   float* E = reinterpret_cast<float*>(lds + render_rows_bytes(M));           // [2][kRB][64]
   int* CI = reinterpret_cast<int*>(E + 2 * kRB * 64);                        // [2][kRB * kRKMax]
   float* CV = reinterpret_cast<float*>(CI + 2 * kRB * kRKMax);               // [2][kRB * kRKMax]
-  volatile int* ctrl = reinterpret_cast<volatile int*>(CV + 2 * kRB * kRKMax);  // live[2], n_batches
+  int* ctrl = reinterpret_cast<int*>(CV + 2 * kRB * kRKMax);  // live[2], n_batches (ordered by the barriers)
 
   const int tile = (int)bn.tile_order[blockIdx.x];                          // longest lists first
   const int tx = tile % bn.tiles_x, ty = tile / bn.tiles_x;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
           todo &= todo - 1ull;
           const int jj = __builtin_amdgcn_readlane(j, sidx);
           const float vv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vr[g]), sidx));
-          if (add) atomicAdd(&myrow[jj], eg * vv);
+          if (add) myrow[jj] += eg * vv;         // one writer per row entry: no atomic needed
         }
       }
     }
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
   uint16_t* Wh = Et + 2 * 64 * kMxRow;                                       // [4][TPW*32][kMxRow]
   int* CI = reinterpret_cast<int*>(Wh + 4 * TPW * 32 * kMxRow);             // [2][kRB * kRKMax]
   float* CV = reinterpret_cast<float*>(CI + 2 * kRB * kRKMax);
-  volatile int* ctrl = reinterpret_cast<volatile int*>(lds + std::max(ra, rb));
+  int* ctrl = reinterpret_cast<int*>(lds + std::max(ra, rb));
 
   const int tile = (int)bn.tile_order[blockIdx.x];
   const int tx = tile % bn.tiles_x, ty = tile / bn.tiles_x;
