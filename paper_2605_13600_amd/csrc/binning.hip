@@ -630,6 +630,10 @@ __global__ __launch_bounds__(1024) void k_sort_big(unsigned long long* __restric
   }
 }
 
+// Compositing order: tiles by list length, longest first, in buckets of one
+// length each below kOrderBuckets - 1 and one bucket for all longer lists.
+constexpr int kOrderBuckets = 2048;
+
 // Depth order inside every block list: one workgroup of NT threads per block
 // whose list has hi/2 < L <= hi = NT x PER pairs (one launch per size class),
 // a bitonic network over hi keys (the list padded with ~0).  Thread t keeps
@@ -652,19 +656,12 @@ __device__ __forceinline__ void bitonic_regs(unsigned long long (&v)[PER], int b
 }
 
 template <int NT, int PER>
-__global__ __launch_bounds__(NT) void k_sort_blocks(unsigned long long* __restrict__ keys,
-                                                    const unsigned int* __restrict__ tile_start, int lo,
-                                                    const Status* st) {
+__device__ void sort_block_list(unsigned long long* __restrict__ s, int L, unsigned long long* sk) {
   constexpr int HI = NT * PER;
-  __shared__ unsigned long long sk[HI];
-  if (st->view_overflow) return;
-  const unsigned int start = tile_start[blockIdx.x];
-  const int L = (int)(tile_start[blockIdx.x + 1] - start);
-  if (L <= lo || L > HI) return;
   const int t = threadIdx.x, base = t * PER;
   unsigned long long v[PER];
 #pragma unroll
-  for (int r = 0; r < PER; ++r) v[r] = base + r < L ? keys[start + base + r] : ~0ull;
+  for (int r = 0; r < PER; ++r) v[r] = base + r < L ? s[base + r] : ~0ull;
   for (int k = 2; k <= HI; k <<= 1) {
     for (int j = k >> 1; j >= PER; j >>= 1) {      // partner in thread t ^ (j / PER), same slot
 #pragma unroll
@@ -686,8 +683,32 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(unsigned long long* __restri
   }
 #pragma unroll
   for (int r = 0; r < PER; ++r)
-    if (base + r < L) keys[start + base + r] = v[r];
+    if (base + r < L) s[base + r] = v[r];
+  __syncthreads();                             // sk is reused by the next list
 }
+
+
+template <int NT, int PER>
+__global__ __launch_bounds__(NT) void k_sort_blocks(unsigned long long* __restrict__ keys,
+                                                    const unsigned int* __restrict__ tile_start,
+                                                    const unsigned int* __restrict__ order, int n_tiles, int lo,
+                                                    const Status* st) {
+  constexpr int HI = NT * PER;
+  __shared__ unsigned long long sk[HI];
+  if (st->view_overflow) return;
+  // the order puts every list of at least kOrderBuckets - 1 keys first (the
+  // only ones this size class can hold), so a workgroup stops at the first
+  // shorter one
+  for (int q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const int tile = (int)order[q];
+    const unsigned int start = tile_start[tile];
+    const int L = (int)(tile_start[tile + 1] - start);
+    if (L < kOrderBuckets - 1) break;
+    if (L <= lo || L > HI) continue;
+    sort_block_list<NT, PER>(keys + start, L, sk);
+  }
+}
+
 
 int radix_passes(int n_tiles) {
   int bits = 1;
@@ -703,7 +724,6 @@ long long scan_blocks(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
 // blocks with the longest sequential loops start at the beginning of the
 // launch instead of setting its tail.  One workgroup; a counting sort on the
 // clamped length.
-constexpr int kOrderBuckets = 2048;
 
 constexpr int kOrderLdsTiles = 32768;          // bucket of each tile kept in LDS up to this many tiles
 
@@ -902,18 +922,8 @@ __global__ __launch_bounds__(256) void k_sort_lists_wave(unsigned long long* __r
 // through LDS (mirror and half-cleaners of 512 and more), registers
 // (256 .. 64) and lanes (32 .. 1).
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __restrict__ keys,
-                                                          const unsigned int* __restrict__ tile_start,
-                                                          const unsigned int* __restrict__ order, int lo,
-                                                          const Status* st) {
-  __shared__ unsigned long long sx[W * 512];
-  if (st->view_overflow) return;
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-  const unsigned int start = tile_start[tile];
-  const int L = (int)(tile_start[tile + 1] - start);
-  if (L <= lo || L > 512 * W) return;
+__device__ void wg_sort_list(unsigned long long* __restrict__ s, int L, unsigned long long* sx) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  unsigned long long* s = keys + start;
   unsigned long long v[8];
 #pragma clang loop unroll(full)
   for (int r = 0; r < 8; ++r) {
@@ -947,6 +957,26 @@ __global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __
   for (int r = 0; r < 8; ++r) {
     const int e = wave * 512 + r * 64 + lane;
     if (e < L) s[e] = v[r];
+  }
+}
+
+// A bounded grid walks the compositing order (longest lists first) and stops
+// at the first list of lo keys or fewer: no workgroup per block of the image.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __restrict__ keys,
+                                                          const unsigned int* __restrict__ tile_start,
+                                                          const unsigned int* __restrict__ order, int n_tiles,
+                                                          int lo, const Status* st) {
+  __shared__ unsigned long long sx[W * 512];
+  if (st->view_overflow) return;
+  for (int q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const int tile = (int)order[q];
+    const unsigned int start = tile_start[tile];
+    const int L = (int)(tile_start[tile + 1] - start);
+    if (L <= lo) break;
+    if (L > 512 * W) continue;
+    wg_sort_list<W>(keys + start, L, sx);
+    __syncthreads();                           // sx is reused by the next list
   }
 }
 
@@ -1039,15 +1069,17 @@ static void sort_lists(const BinArgs& a, hipStream_t s, bool order_done) {
   hipLaunchKernelGGL(k_sort_big, dim3(16), dim3(1024), 0, s, a.keys[a.sorted], a.tile_start, a.big_tiles,
                      a.status);
   if (a.n_tiles > 0) {            // 2 .. 512 keys: one wave per list; .. 2048: 2 or 4 waves; .. 4096 (= kSortCap)
+    // the longer classes walk the longest-first order (bounded grids where few lists are that long)
     unsigned long long* k = a.keys[a.sorted];
-    const dim3 g(a.n_tiles);
-    hipLaunchKernelGGL(k_sort_lists_wave, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, k, a.tile_start,
-                       a.tile_order, a.n_tiles, a.status);
-    hipLaunchKernelGGL(k_sort_lists_wg<2>, g, dim3(128), 0, s, k, a.tile_start, a.tile_order, kWaveSortMax,
-                       a.status);
-    hipLaunchKernelGGL(k_sort_lists_wg<4>, g, dim3(256), 0, s, k, a.tile_start, a.tile_order, 2 * kWaveSortMax,
-                       a.status);
-    hipLaunchKernelGGL((k_sort_blocks<512, 8>), g, dim3(512), 0, s, k, a.tile_start, kWgSortMax, a.status);
+    const int nt = a.n_tiles;
+    hipLaunchKernelGGL(k_sort_lists_wave, dim3((nt + 3) / 4), dim3(256), 0, s, k, a.tile_start,
+                       a.tile_order, nt, a.status);
+    hipLaunchKernelGGL(k_sort_lists_wg<2>, dim3(nt), dim3(128), 0, s, k, a.tile_start, a.tile_order,
+                       nt, kWaveSortMax, a.status);
+    hipLaunchKernelGGL(k_sort_lists_wg<4>, dim3(std::min(nt, 2048)), dim3(256), 0, s, k, a.tile_start, a.tile_order,
+                       nt, 2 * kWaveSortMax, a.status);
+    hipLaunchKernelGGL((k_sort_blocks<512, 8>), dim3(std::min(nt, 256)), dim3(512), 0, s, k, a.tile_start,
+                       a.tile_order, nt, kWgSortMax, a.status);
   }
 }
 

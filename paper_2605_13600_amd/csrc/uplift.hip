@@ -93,7 +93,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   const unsigned int start = tile_start[tile];
   const int L = (int)(tile_start[tile + 1] - start);
   const int lane = threadIdx.x;
-  const int lx = lane & 7, ly = lane >> 3;
+  // lanes 16 q .. 16 q + 15 hold the 4x4 quadrant q of the block (every
+  // per-pixel mask below is a ballot over lanes, so the order is free)
+  const int qd = lane >> 4, qi = lane & 15;
+  const int lx = (qd & 1) * 4 + (qi & 3), ly = (qd >> 1) * 4 + (qi >> 2);
   const int tile_x0 = tx * 8, tile_y0 = ty * 8;
   const int px = tile_x0 + lx, py = tile_y0 + ly;
   const bool inside = px < W && py < H;
@@ -190,6 +193,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 #pragma unroll
   for (int l = 0; l < NL; ++l)
     if (rec_col && (col >> 1) == l) rec_out = args.lv[l].records;
+  if (lane == 0) {                             // slot B: a Gaussian never taken (steps past a quadrant's list)
+    s_bs[2 * B] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    s_bs[2 * B + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    s_q[B] = -1.0f;
+  }
   __syncthreads();                             // column data read before E is overwritten
 
   const float pcx = (float)lx + 0.5f, pcy = (float)ly + 0.5f;
@@ -216,10 +224,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const unsigned int off_next = sp_next.depth_bits;
     const unsigned long long key_after = keys[start + min(j + 2 * B, L - 1)];
     unsigned int my_id = 0;
+    unsigned int qmask = 0u;                   // lane < B: quadrants of the block Gaussian gk's box reaches
     if (j < L) {
       my_id = (unsigned int)key_cur;
-      if (lane < B) {                          // LDS copy read back as a broadcast in the loop
+      if (lane < B) {                          // LDS copy read back in the loop
         const GSplat gg = sp_cur;
+        const int ex0 = gg.bx0 - tile_x0, ex1 = gg.bx1 - tile_x0, ey0 = gg.by0 - tile_y0, ey1 = gg.by1 - tile_y0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int qx = (q & 1) * 4, qy = (q >> 1) * 4;
+          if (ex0 <= qx + 3 && ex1 >= qx && ey0 <= qy + 3 && ey1 >= qy) qmask |= 1u << q;
+        }
         BlockSplat bs;
         bs.load(gg, tile_x0, tile_y0);
         s_bs[2 * lane] = make_float4(bs.hx, bs.hy, bs.fx, bs.fy);
@@ -231,14 +246,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       }
     }
     __syncthreads();
-    int kend = 0;                              // E rows 0 .. kend-1 written in this batch
+    // Each quadrant steps through the batch Gaussians whose box reaches it, in
+    // list order: a Gaussian skipped by a quadrant has alpha < 1/255 at all of
+    // its pixels, so the recurrence is unchanged.  E rows start at zero (the
+    // weights of skipped (Gaussian, pixel) pairs).
+    const unsigned int qb0 = (unsigned int)__ballot(qmask & 1u), qb1 = (unsigned int)__ballot((qmask >> 1) & 1u);
+    const unsigned int qb2 = (unsigned int)__ballot((qmask >> 2) & 1u), qb3 = (unsigned int)__ballot((qmask >> 3) & 1u);
+    {
+      float4* e4 = reinterpret_cast<float4*>(E);
+      for (int c = lane; c < B * (kEStride / 4); c += 64) e4[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     unsigned long long any_e = 0ull;           // pixels with some e > 0 in this batch
+    __syncthreads();
     if (!all_done) {
-      // One Gaussian of the batch, without branches.  T is -1 on a finished
-      // pixel (or one outside the image) and at least kTMin otherwise, so a
-      // Gaussian below the alpha threshold can run the same arithmetic with
-      // alpha = 0: testT = T exactly, E = 0, T kept; on a finished pixel
-      // testT < 0 fails the kTMin test and T stays -1.
+      // One Gaussian, without branches.  T is -1 on a finished pixel (or one
+      // outside the image) and at least kTMin otherwise, so a Gaussian below
+      // the alpha threshold can run the same arithmetic with alpha = 0: testT
+      // = T exactly, E = 0, T kept; on a finished pixel testT < 0 fails the
+      // kTMin test and T stays -1.  Slot B is a Gaussian never taken (qmax < 0).
       auto step = [&](int k, const float4& c0, const float4& c1, float cq) {
         // c0 = (hx, hy, fx, fy), c1 = (l00, l10, l11, opacity), cq = qmax
         const float dx = (pcx - c0.x) - c0.z, dy = (pcy - c0.y) - c0.w;
@@ -249,32 +274,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const float testT = T * (1.0f - alpha);
         const bool keep = testT >= kTMin;
         const float e = keep ? alpha * T : 0.0f;   // > 0 exactly when the Gaussian was taken and kept
-        E[k * kEStride + lane] = e;
+        if (k < B) E[k * kEStride + lane] = e;
         T = keep ? testT : -1.0f;
         const unsigned long long kb = __ballot(e > 0.0f);   // scalar bookkeeping
         any_e |= kb;
         count += (unsigned long long)__popcll(kb);
       };
-      // two register sets alternate so that each Gaussian's splat is read
-      // from LDS one step ahead without copies
-      float4 a0 = s_bs[0], a1 = s_bs[1];
-      float aq = s_q[0];
-      for (int k = 0; k < nb; k += 2) {
-        // slots past the batch hold stale data; they are never used
-        const float4 b0v = s_bs[2 * k + 2], b1v = s_bs[2 * k + 3];
-        const float bq = s_q[k + 1];
-        step(k, a0, a1, aq);
-        kend = k + 1;
-        if (k + 1 >= nb) break;
-        a0 = s_bs[2 * k + 4]; a1 = s_bs[2 * k + 5]; aq = s_q[k + 2];
-        step(k + 1, b0v, b1v, bq);
-        kend = k + 2;
+      unsigned int bq = (qd & 2) ? ((qd & 1) ? qb3 : qb2) : ((qd & 1) ? qb1 : qb0);
+      const int nsteps = max(max(__popc(qb0), __popc(qb1)), max(__popc(qb2), __popc(qb3)));
+      auto next = [&]() {
+        const int k = bq ? __ffs(bq) - 1 : B;
+        bq &= bq - 1u;
+        return k;
+      };
+      // two register sets alternate so that each step's splat is read from
+      // LDS one step ahead without copies
+      int ka = next();
+      float4 a0 = s_bs[2 * ka], a1 = s_bs[2 * ka + 1];
+      float aq = s_q[ka];
+      for (int k = 0; k < nsteps; k += 2) {
+        const int kb2 = next();
+        const float4 b0v = s_bs[2 * kb2], b1v = s_bs[2 * kb2 + 1];
+        const float bq2 = s_q[kb2];
+        step(ka, a0, a1, aq);
+        if (k + 1 >= nsteps) break;
+        ka = next();
+        a0 = s_bs[2 * ka]; a1 = s_bs[2 * ka + 1]; aq = s_q[ka];
+        step(kb2, b0v, b1v, bq2);
         if (__ballot(T > 0.0f) == 0ull) break;
       }
     }
-    // bit k: E row k is this batch's (rows past kend hold an earlier batch's
-    // weights and count as zero); none when no pixel got a weight
-    const unsigned long long contributed = any_e ? (kend >= 32 ? 0xFFFFFFFFull : (1ull << kend) - 1ull) : 0ull;
+    // bit k: E row k belongs to this batch's Gaussian k (zero where it was not
+    // evaluated); none when no pixel got a weight
+    const unsigned long long contributed = any_e ? (nb >= 32 ? 0xFFFFFFFFull : (1ull << nb) - 1ull) : 0ull;
     __syncthreads();
     if (two_class) {
       // lane group g sums Gaussian gk's row over the group's pixels of each
