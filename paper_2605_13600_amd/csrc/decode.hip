@@ -178,7 +178,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
         const int off = k0 * F::ES + q * 16;
         if (p < P) {
           const uint8_t* src = A + p * src_row + off;
-          for (int b = 0; b < 16 && off + b < src_row; ++b) reinterpret_cast<uint8_t*>(&v)[b] = src[b];
+          unsigned int w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int b = 0; b < 16; ++b)
+            if (off + b < src_row) w[b >> 2] |= (unsigned int)src[b] << (8 * (b & 3));
+          v = (i32x4){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
         }
         *reinterpret_cast<i32x4*>(sA + r * row_bytes + q * 16) = v;
       }
@@ -291,6 +295,184 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Codebook-stationary decode (BF16 / FP8 input, D <= 512, BF16 M <= 256, FP8
+// M <= 512): wave w holds the B fragments of column tile w for every k-step
+// in registers for the whole launch, so the codebook is read once per wave
+// instead of once per pixel tile.  Tiles of 64 pixels stream through a
+// double-buffered LDS block (the next tile's row loads are in flight while
+// the current one is multiplied); each 32-pixel half of the output goes
+// through LDS and leaves as 16-byte pieces of whole rows.
+// ---------------------------------------------------------------------------
+constexpr int kBsRows = 64;                   // pixels per tile
+// k-steps held in registers: 64 registers of codebook fragments (BF16: M <= 256; FP8: M <= 512)
+template <int T> struct BsKs { static constexpr int N = T == SCOUP_BF16 ? 16 : 8; };
+
+__host__ __device__ inline int bs_row_bytes(int kpad, int es) { return kpad * es + 16; }
+__host__ __device__ inline int bs_stage_stride(int d, int oes) { return ((d * oes + 15) & ~15) + 16; }
+
+template <int T, typename TOut>
+__global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ A, long long P, int M, int kpad,
+                                                    const uint8_t* __restrict__ Bp, int n_valid, int ldo,
+                                                    TOut* __restrict__ out, float out_mul,
+                                                    const float* __restrict__ cb_scale) {
+  using F = Mfma<T>;
+  using FT = typename Frag<T>::type;
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int nw = blockDim.x >> 6;                     // waves = column tiles
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nks = kpad / F::KS;
+  const int rb = bs_row_bytes(kpad, F::ES);
+  uint8_t* sA0 = lds;
+  uint8_t* sA1 = lds + (size_t)kBsRows * rb;
+  constexpr int OES = (int)sizeof(TOut);
+  const int sstride = bs_stage_stride(n_valid, OES);
+  uint8_t* stage = lds + 2 * (size_t)kBsRows * rb;
+  float mul = out_mul;
+  if (cb_scale) mul /= *cb_scale;
+  // the wave's codebook column tile, every k-step
+  constexpr int MAXKS = BsKs<T>::N;
+  FT bf[MAXKS];
+  {
+    const FT* Bf = reinterpret_cast<const FT*>(Bp);
+#pragma unroll
+    for (int ks = 0; ks < MAXKS; ++ks)
+      if (ks < nks) bf[ks] = Bf[((long long)wave * nks + ks) * 64 + lane];
+  }
+  const long long n_tiles = (P + kBsRows - 1) / kBsRows;
+  const int src_row = M * F::ES;
+  const int chunks = kpad * F::ES / 16;              // 16-byte pieces per staged row
+  const int per_tile = kBsRows * chunks;
+  const bool vec_src = (src_row & 15) == 0;
+  // a thread's pieces of tile t: c = tid + u nthreads
+  const int nthr = blockDim.x;
+  auto load_piece = [&](long long t, int c) -> i32x4 {
+    i32x4 v = {0, 0, 0, 0};
+    const int r = c / chunks, q = c - r * chunks;
+    const long long p = t * kBsRows + r;
+    const int off = q * 16;
+    if (c < per_tile && p < P) {
+      const uint8_t* src = A + p * src_row + off;
+      if (vec_src) {
+        if (off + 16 <= src_row) v = *reinterpret_cast<const i32x4*>(src);
+      } else {
+        unsigned int w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+          if (off + b < src_row) w[b >> 2] |= (unsigned int)src[b] << (8 * (b & 3));
+        v = (i32x4){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+      }
+    }
+    return v;
+  };
+  auto put_piece = [&](uint8_t* sA, int c, i32x4 v) {
+    if (c < per_tile) {
+      const int r = c / chunks, q = c - r * chunks;
+      *reinterpret_cast<i32x4*>(sA + r * rb + q * 16) = v;
+    }
+  };
+  constexpr int U = 2;                                // pieces a thread loads ahead (a BF16 M = 256 tile at 1024 threads)
+  long long t = blockIdx.x;
+  if (t < n_tiles) {
+    for (int c0 = tid; c0 < per_tile; c0 += nthr * U) {
+      i32x4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = load_piece(t, c0 + u * nthr);
+#pragma unroll
+      for (int u = 0; u < U; ++u) put_piece(sA0, c0 + u * nthr, v[u]);
+    }
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; t < n_tiles; t += gridDim.x) {
+    uint8_t* sA = buf ? sA1 : sA0;
+    uint8_t* sN = buf ? sA0 : sA1;
+    const long long tn = t + gridDim.x;
+    // the next tile's rows: loads issued now, stored after the multiplies
+    i32x4 nv[U];
+    const bool more = tn < n_tiles && per_tile <= nthr * U;
+#pragma unroll
+    for (int u = 0; u < U; ++u) nv[u] = more ? load_piece(tn, tid + u * nthr) : (i32x4){0, 0, 0, 0};
+    // element r of lane l: pixel h 32 + l % 32, feature 32 wave + 8 (r / 4) + 4 (l / 32) + r % 4
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f16v acc = (f16v){};
+#pragma unroll
+      for (int ks = 0; ks < MAXKS; ++ks) {
+        if (ks < nks) {
+          const int kb = (ks * F::KS + (lane >> 5) * (F::KS / 2)) * F::ES;
+          const FT a = *reinterpret_cast<const FT*>(sA + (h * 32 + (lane & 31)) * rb + kb);
+          acc = Frag<T>::mfma(bf[ks], a, acc);
+        }
+      }
+      if (h == 0 && more) {
+        // the next tile's rows into the other buffer (free since the last tile's
+        // barriers; read after the barriers below)
+#pragma unroll
+        for (int u = 0; u < U; ++u) put_piece(sN, tid + u * nthr, nv[u]);
+      }
+      TOut* row = reinterpret_cast<TOut*>(stage + (lane & 31) * sstride);
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg) {
+        const int d0 = wave * 32 + 8 * rg + 4 * (lane >> 5);
+        if (d0 + 3 < n_valid) {
+          store4(row + d0, acc[4 * rg] * mul, acc[4 * rg + 1] * mul, acc[4 * rg + 2] * mul, acc[4 * rg + 3] * mul);
+        } else {
+          if (d0 < n_valid) store_f(row + d0, acc[4 * rg] * mul);
+          if (d0 + 1 < n_valid) store_f(row + d0 + 1, acc[4 * rg + 1] * mul);
+          if (d0 + 2 < n_valid) store_f(row + d0 + 2, acc[4 * rg + 2] * mul);
+        }
+      }
+      __syncthreads();
+      const long long p0 = t * kBsRows + h * 32;
+      const int rbytes = n_valid * OES;
+      const bool vec = (rbytes & 15) == 0 && (((long long)ldo * OES) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+      uint8_t* ob = reinterpret_cast<uint8_t*>(out);
+      if (vec) {
+        const int pieces = rbytes / 16;
+        for (int c = tid; c < 32 * pieces; c += nthr) {
+          const int r = c / pieces, q = c - r * pieces;
+          if (p0 + r < P)
+            *reinterpret_cast<i32x4*>(ob + (p0 + r) * (long long)ldo * OES + q * 16) =
+                *reinterpret_cast<const i32x4*>(stage + r * sstride + q * 16);
+        }
+      } else {
+        for (int c = tid; c < 32 * rbytes; c += nthr) {
+          const int r = c / rbytes, b = c - r * rbytes;
+          if (p0 + r < P) ob[(p0 + r) * (long long)ldo * OES + b] = stage[r * sstride + b];
+        }
+      }
+      __syncthreads();
+    }
+    if (!more && tn < n_tiles) {                     // rows longer than one pass of loads
+      for (int c0 = tid; c0 < per_tile; c0 += nthr * U) {
+        i32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load_piece(tn, c0 + u * nthr);
+#pragma unroll
+        for (int u = 0; u < U; ++u) put_piece(sN, c0 + u * nthr, v[u]);
+      }
+      __syncthreads();
+    }
+    buf ^= 1;
+  }
+}
+
+size_t decode_bs_lds_bytes(const DecodeArgs& a) {
+  const int es = a.in_dtype == SCOUP_BF16 ? 2 : 1;
+  const int oes = a.out_dtype == SCOUP_F32 ? 4 : 2;
+  return 2 * (size_t)kBsRows * bs_row_bytes(a.kpad, es) + 32 * (size_t)bs_stage_stride(a.d, oes);
+}
+
+// BF16 / FP8 input, at most 16 column tiles and kBsMaxKs k-steps, LDS within 160 KB
+bool decode_uses_bs(const DecodeArgs& a) {
+  if (a.in_dtype != SCOUP_BF16 && a.in_dtype != SCOUP_FP8_E4M3) return false;
+  const int ks = a.in_dtype == SCOUP_BF16 ? 16 : 64;
+  const int maxks = a.in_dtype == SCOUP_BF16 ? BsKs<SCOUP_BF16>::N : BsKs<SCOUP_FP8_E4M3>::N;
+  return decode_npad(a.d) <= 512 && a.kpad / ks <= maxks && decode_bs_lds_bytes(a) <= 160 * 1024;
+}
+
 int decode_npad(int d) {
   if (d <= 128) return 128;
   if (d <= 256) return 256;
@@ -377,6 +559,11 @@ hipError_t decode_set_lds_limits() {
   SETL(SCOUP_F32, float) SETL(SCOUP_F32, uint16_t) SETL(SCOUP_BF16, float) SETL(SCOUP_BF16, uint16_t)
   SETL(SCOUP_FP8_E4M3, float) SETL(SCOUP_FP8_E4M3, uint16_t)
 #undef SETL
+  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_BF16, float>, attr, (int)b)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_BF16, uint16_t>, attr, (int)b)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_FP8_E4M3, float>, attr, (int)b)) != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_FP8_E4M3, uint16_t>, attr, (int)b);
   return e;
 }
 
@@ -413,6 +600,24 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage) {
   const int grid = (int)std::min<long long>(tiles, kDecGrid);   // workgroups walk the tiles
   StageTimer::begin(stage, s);
   hipError_t e;
+  if (decode_uses_bs(a)) {
+    const int nw = decode_npad(a.d) / 32;
+    const long long bt = (a.P + kBsRows - 1) / kBsRows;
+    const int g = (int)std::min<long long>(bt, 256);           // one workgroup per CU
+    const size_t bl = decode_bs_lds_bytes(a);
+    const int ldo = a.ldo > 0 ? a.ldo : a.d;
+#define BS_LAUNCH(T, TO)                                                                                       \
+  hipLaunchKernelGGL((k_decode_bs<T, TO>), dim3(g), dim3(64 * nw), bl, s, (const uint8_t*)a.coeff, a.P, a.m,     \
+                     a.kpad, (const uint8_t*)a.codebook_prep, a.d, ldo, (TO*)a.out, a.out_mul, a.cb_scale)
+    if (a.in_dtype == SCOUP_BF16) {
+      if (a.out_dtype == SCOUP_F32) BS_LAUNCH(SCOUP_BF16, float); else BS_LAUNCH(SCOUP_BF16, uint16_t);
+    } else {
+      if (a.out_dtype == SCOUP_F32) BS_LAUNCH(SCOUP_FP8_E4M3, float); else BS_LAUNCH(SCOUP_FP8_E4M3, uint16_t);
+    }
+#undef BS_LAUNCH
+    StageTimer::end(stage, s);
+    return hipGetLastError();
+  }
   if (a.in_dtype == SCOUP_F32)
     e = a.out_dtype == SCOUP_F32 ? dispatch_nct<SCOUP_F32, float>(a, s, lds, grid)
                                  : dispatch_nct<SCOUP_F32, uint16_t>(a, s, lds, grid);
