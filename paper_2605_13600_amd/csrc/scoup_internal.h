@@ -135,7 +135,7 @@ struct RenderBlockArgs {
   void* features;          // [P x d] of out_dtype
 };
 hipError_t launch_render_block(RenderBlockArgs& a, hipStream_t s, int stage);
-size_t render_block_lds_bytes(int m, int npad, int out_dtype);
+size_t render_block_lds_bytes(const RenderBlockArgs& a);
 hipError_t render_set_lds_limits();
 
 struct DecodeArgs {
