@@ -195,8 +195,9 @@ size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam
 /* Eq. 7 for one camera: coeff_map[p*m + j] = coeff_scale * sum over Gaussians i
  * in N_{v,p} (same compositing as the uplift) of e_i(v,p) * topk_val[i*k + s]
  * for every slot s with topk_idx[i*k + s] == j (slots with index -1 are
- * skipped).  Accumulation is float32, each map entry summed in the pixel's
- * front-to-back order (bit-reproducible); the map is written once per pixel in
+ * skipped).  The products e * topk_val are float32 and are summed in float32
+ * on the matrix cores, two Gaussians at a time in the block's front-to-back
+ * list order (a fixed order: bit-reproducible); the map is written once per pixel in
  * coeff_dtype (F32, BF16 round-to-nearest-even, or FP8 E4M3 saturating; use
  * coeff_scale to place FP8 values in range, e.g. 256 since coefficients are
  * at most 1).
@@ -226,9 +227,13 @@ size_t scoup_render_decode_workspace_bytes(int64_t n_gaussians, const scoup_came
  * unless coeff_map asks for it.  in_dtype is the precision of that product:
  * F32; BF16 (rows and codebook rounded to nearest even); FP8 E4M3 (rows times
  * 256, codebook times a power-of-two scale, both divided out in float32).
- * The features equal scoup_decode applied to the scoup_render_coeff map of
- * the same precision (F32 map, BF16 map, FP8 map with coeff_scale 256), bit
- * for bit.  Pixels without a contribution get zero features.
+ * With in_dtype F32, or whenever coeff_map is given, the rows are those of
+ * scoup_render_coeff and the features equal scoup_decode applied to the
+ * scoup_render_coeff map of the same precision (F32 map, BF16 map, FP8 map
+ * with coeff_scale 256), bit for bit.  BF16 / FP8 without coeff_map sum the
+ * rows from bfloat16-rounded products e * topk_val instead (one bfloat16
+ * rounding per term; the result is still bit-reproducible).  Pixels without a
+ * contribution get zero features.
  *   topk_idx/val   device [n*k], 1 <= k <= 16, indices < m_atoms (else SCOUP_E_DATA)
  *   codebook       device float32 [m_atoms*dim], 1 <= m_atoms <= 512, 1 <= dim <= 1024
  *   coeff_map      device float32 [H*W*m_atoms] (the float32 W_hat, as for the
