@@ -300,18 +300,32 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
 // M <= 512): wave w holds the B fragments of column tile w for every k-step
 // in registers for the whole launch, so the codebook is read once per wave
 // instead of once per pixel tile.  Tiles of 64 pixels stream through a
-// double-buffered LDS block (the next tile's row loads are in flight while
-// the current one is multiplied); each 32-pixel half of the output goes
-// through LDS and leaves as 16-byte pieces of whole rows.
+// double-buffered LDS block: the next tile's rows are loaded into registers
+// when a tile starts and reach LDS after its multiplies, so the tile's work
+// hides their latency.  Each 32-pixel half of the output goes through
+// its own LDS staging area (one shared area when two do not fit) and leaves
+// as 16-byte pieces of whole rows; with two areas no barrier waits for the
+// stores.  The k loop has a compile-time length NKS >= the k-steps (padding
+// steps multiply zero rows by a zero codebook fragment), so it is
+// straight-line code with constant LDS offsets.
 // ---------------------------------------------------------------------------
 constexpr int kBsRows = 64;                   // pixels per tile
 // k-steps held in registers: 64 registers of codebook fragments (BF16: M <= 256; FP8: M <= 512)
 template <int T> struct BsKs { static constexpr int N = T == SCOUP_BF16 ? 16 : 8; };
 
-__host__ __device__ inline int bs_row_bytes(int kpad, int es) { return kpad * es + 16; }
+// the k loop's compile-time length: the k-steps rounded up to a quarter, a
+// half or all of the register budget n; the staged rows span that many
+// k-steps (zero past kpad)
+__host__ __device__ constexpr int bs_nks(int nks, int n) { return nks <= n / 4 ? n / 4 : nks <= n / 2 ? n / 2 : n; }
+__host__ __device__ constexpr int bs_row_bytes(int kfull, int es) { return kfull * es + 16; }
 __host__ __device__ inline int bs_stage_stride(int d, int oes) { return ((d * oes + 15) & ~15) + 16; }
+// staging areas: two when they fit beside the double-buffered tile
+__host__ __device__ inline int bs_n_stage(int kpad, int es, int d, int oes) {
+  return 2 * (size_t)kBsRows * bs_row_bytes(kpad, es) + 2 * 32 * (size_t)bs_stage_stride(d, oes) <= 160 * 1024 ? 2
+                                                                                                          : 1;
+}
 
-template <int T, typename TOut>
+template <int T, typename TOut, int NKS>
 __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ A, long long P, int M, int kpad,
                                                     const uint8_t* __restrict__ Bp, int n_valid, int ldo,
                                                     TOut* __restrict__ out, float out_mul,
@@ -319,26 +333,29 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
   using F = Mfma<T>;
   using FT = typename Frag<T>::type;
   extern __shared__ __align__(16) uint8_t lds[];
-  const int nw = blockDim.x >> 6;                     // waves = column tiles
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int nks = kpad / F::KS;
-  const int rb = bs_row_bytes(kpad, F::ES);
+  const int nks = kpad / F::KS;                       // 1 <= nks <= NKS
+  constexpr int rb = bs_row_bytes(NKS * F::KS, F::ES);
   uint8_t* sA0 = lds;
   uint8_t* sA1 = lds + (size_t)kBsRows * rb;
   constexpr int OES = (int)sizeof(TOut);
   const int sstride = bs_stage_stride(n_valid, OES);
-  uint8_t* stage = lds + 2 * (size_t)kBsRows * rb;
+  const int nst = bs_n_stage(NKS * F::KS, F::ES, n_valid, OES);
+  uint8_t* stage0 = lds + 2 * (size_t)kBsRows * rb;
   float mul = out_mul;
   if (cb_scale) mul /= *cb_scale;
-  // the wave's codebook column tile, every k-step
-  constexpr int MAXKS = BsKs<T>::N;
-  FT bf[MAXKS];
+  // the wave's codebook column tile, every k-step (zero past nks), complete
+  // before the loop so that no multiply waits on memory
+  FT bf[NKS];
   {
     const FT* Bf = reinterpret_cast<const FT*>(Bp);
 #pragma unroll
-    for (int ks = 0; ks < MAXKS; ++ks)
-      if (ks < nks) bf[ks] = Bf[((long long)wave * nks + ks) * 64 + lane];
+    for (int ks = 0; ks < NKS; ++ks) bf[ks] = Bf[((long long)wave * nks + min(ks, nks - 1)) * 64 + lane];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+      if (ks >= nks) bf[ks] = FT{};
   }
+  __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
   const long long n_tiles = (P + kBsRows - 1) / kBsRows;
   const int src_row = M * F::ES;
   const int chunks = kpad * F::ES / 16;              // 16-byte pieces per staged row
@@ -372,6 +389,13 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
     }
   };
   constexpr int U = 2;                                // pieces a thread loads ahead (a BF16 M = 256 tile at 1024 threads)
+  {                                                   // the rows' k padding, both buffers: zero for good
+    const int pc = (NKS * F::KS - kpad) * F::ES / 16;
+    for (int c = tid; c < 2 * kBsRows * pc; c += nthr) {
+      const int r = c / pc, q = c - r * pc;
+      *reinterpret_cast<i32x4*>(lds + (size_t)r * rb + kpad * F::ES + q * 16) = (i32x4){0, 0, 0, 0};
+    }
+  }
   long long t = blockIdx.x;
   if (t < n_tiles) {
     for (int c0 = tid; c0 < per_tile; c0 += nthr * U) {
@@ -383,6 +407,10 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
     }
   }
   __syncthreads();
+  const int rbytes = n_valid * OES;
+  const bool vec = (rbytes & 15) == 0 && (((long long)ldo * OES) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+  uint8_t* ob = reinterpret_cast<uint8_t*>(out);
   int buf = 0;
   for (; t < n_tiles; t += gridDim.x) {
     uint8_t* sA = buf ? sA1 : sA0;
@@ -397,20 +425,26 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       f16v acc = (f16v){};
+      const uint8_t* arow = sA + (h * 32 + (lane & 31)) * rb + (lane >> 5) * (F::KS / 2) * F::ES;
+      if constexpr (T == SCOUP_FP8_E4M3 && NKS == BsKs<T>::N) {
+        // one k-step per branch: straight-line code would let the scheduler
+        // hoist every 8-register FP8 operand ahead of the multiplies and spill
 #pragma unroll
-      for (int ks = 0; ks < MAXKS; ++ks) {
-        if (ks < nks) {
-          const int kb = (ks * F::KS + (lane >> 5) * (F::KS / 2)) * F::ES;
-          const FT a = *reinterpret_cast<const FT*>(sA + (h * 32 + (lane & 31)) * rb + kb);
-          acc = Frag<T>::mfma(bf[ks], a, acc);
-        }
+        for (int ks = 0; ks < NKS; ++ks)
+          if (ks < nks) acc = Frag<T>::mfma(bf[ks], *reinterpret_cast<const FT*>(arow + ks * F::KS * F::ES), acc);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+          acc = Frag<T>::mfma(bf[ks], *reinterpret_cast<const FT*>(arow + ks * F::KS * F::ES), acc);
       }
-      if (h == 0 && more) {
-        // the next tile's rows into the other buffer (free since the last tile's
-        // barriers; read after the barriers below)
+      if (h == 1 && more) {
+        // the next tile's rows into the other buffer (its last reader, the
+        // previous tile's multiplies, is behind the previous barriers; the
+        // next tile reads it after the barrier below)
 #pragma unroll
         for (int u = 0; u < U; ++u) put_piece(sN, tid + u * nthr, nv[u]);
       }
+      uint8_t* stage = stage0 + (nst == 2 ? h : 0) * 32 * (size_t)sstride;
       TOut* row = reinterpret_cast<TOut*>(stage + (lane & 31) * sstride);
 #pragma unroll
       for (int rg = 0; rg < 4; ++rg) {
@@ -425,10 +459,6 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
       }
       __syncthreads();
       const long long p0 = t * kBsRows + h * 32;
-      const int rbytes = n_valid * OES;
-      const bool vec = (rbytes & 15) == 0 && (((long long)ldo * OES) & 15) == 0 &&
-                       (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-      uint8_t* ob = reinterpret_cast<uint8_t*>(out);
       if (vec) {
         const int pieces = rbytes / 16;
         for (int c = tid; c < 32 * pieces; c += nthr) {
@@ -443,7 +473,9 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
           if (p0 + r < P) ob[(p0 + r) * (long long)ldo * OES + b] = stage[r * sstride + b];
         }
       }
-      __syncthreads();
+      // one shared staging area: read out before the next half writes it.
+      // Two: the next writer of this one is a half away, behind its barrier
+      if (nst == 1) __syncthreads();
     }
     if (!more && tn < n_tiles) {                     // rows longer than one pass of loads
       for (int c0 = tid; c0 < per_tile; c0 += nthr * U) {
@@ -462,7 +494,11 @@ __global__ __launch_bounds__(1024) void k_decode_bs(const uint8_t* __restrict__ 
 size_t decode_bs_lds_bytes(const DecodeArgs& a) {
   const int es = a.in_dtype == SCOUP_BF16 ? 2 : 1;
   const int oes = a.out_dtype == SCOUP_F32 ? 4 : 2;
-  return 2 * (size_t)kBsRows * bs_row_bytes(a.kpad, es) + 32 * (size_t)bs_stage_stride(a.d, oes);
+  const int ks = a.in_dtype == SCOUP_BF16 ? 16 : 64;
+  const int n = a.in_dtype == SCOUP_BF16 ? BsKs<SCOUP_BF16>::N : BsKs<SCOUP_FP8_E4M3>::N;
+  const int kfull = bs_nks(a.kpad / ks, n) * ks;
+  return 2 * (size_t)kBsRows * bs_row_bytes(kfull, es) +
+         bs_n_stage(kfull, es, a.d, oes) * 32 * (size_t)bs_stage_stride(a.d, oes);
 }
 
 // BF16 / FP8 input, at most 16 column tiles and kBsMaxKs k-steps, LDS within 160 KB
@@ -548,6 +584,31 @@ static hipError_t set_lds(size_t bytes) {
                              (int)bytes);
 }
 
+template <int T, typename TOut>
+static void launch_bs(const DecodeArgs& a, int g, int nw, size_t bl, int ldo, hipStream_t s) {
+  constexpr int N = BsKs<T>::N;
+  const int nks = a.kpad / Mfma<T>::KS;
+#define BS_LAUNCH(NK)                                                                                            \
+  hipLaunchKernelGGL((k_decode_bs<T, TOut, NK>), dim3(g), dim3(64 * nw), bl, s, (const uint8_t*)a.coeff, a.P, a.m, \
+                     a.kpad, (const uint8_t*)a.codebook_prep, a.d, ldo, (TOut*)a.out, a.out_mul, a.cb_scale)
+  switch (bs_nks(nks, N)) {
+    case N / 4: BS_LAUNCH(N / 4); break;
+    case N / 2: BS_LAUNCH(N / 2); break;
+    default: BS_LAUNCH(N); break;
+  }
+#undef BS_LAUNCH
+}
+
+template <int T, typename TOut>
+static hipError_t set_bs_lds(int b) {
+  constexpr int N = BsKs<T>::N;
+  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<T, TOut, N / 4>, attr, b)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<T, TOut, N / 2>, attr, b)) != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_decode_bs<T, TOut, N>, attr, b);
+}
+
 hipError_t decode_set_lds_limits() {
   const size_t b = 160 * 1024;
   hipError_t e = hipSuccess;
@@ -559,12 +620,10 @@ hipError_t decode_set_lds_limits() {
   SETL(SCOUP_F32, float) SETL(SCOUP_F32, uint16_t) SETL(SCOUP_BF16, float) SETL(SCOUP_BF16, uint16_t)
   SETL(SCOUP_FP8_E4M3, float) SETL(SCOUP_FP8_E4M3, uint16_t)
 #undef SETL
-  const auto attr = hipFuncAttributeMaxDynamicSharedMemorySize;
-  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_BF16, float>, attr, (int)b)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_BF16, uint16_t>, attr, (int)b)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_FP8_E4M3, float>, attr, (int)b)) != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_decode_bs<SCOUP_FP8_E4M3, uint16_t>, attr, (int)b);
-  return e;
+  if ((e = set_bs_lds<SCOUP_BF16, float>((int)b)) != hipSuccess) return e;
+  if ((e = set_bs_lds<SCOUP_BF16, uint16_t>((int)b)) != hipSuccess) return e;
+  if ((e = set_bs_lds<SCOUP_FP8_E4M3, float>((int)b)) != hipSuccess) return e;
+  return set_bs_lds<SCOUP_FP8_E4M3, uint16_t>((int)b);
 }
 
 hipError_t launch_prep_codebook(const float* C, int m, int d, int in_dtype, void* out, float* scale,
@@ -606,15 +665,13 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t s, int stage) {
     const int g = (int)std::min<long long>(bt, 256);           // one workgroup per CU
     const size_t bl = decode_bs_lds_bytes(a);
     const int ldo = a.ldo > 0 ? a.ldo : a.d;
-#define BS_LAUNCH(T, TO)                                                                                       \
-  hipLaunchKernelGGL((k_decode_bs<T, TO>), dim3(g), dim3(64 * nw), bl, s, (const uint8_t*)a.coeff, a.P, a.m,     \
-                     a.kpad, (const uint8_t*)a.codebook_prep, a.d, ldo, (TO*)a.out, a.out_mul, a.cb_scale)
     if (a.in_dtype == SCOUP_BF16) {
-      if (a.out_dtype == SCOUP_F32) BS_LAUNCH(SCOUP_BF16, float); else BS_LAUNCH(SCOUP_BF16, uint16_t);
+      if (a.out_dtype == SCOUP_F32) launch_bs<SCOUP_BF16, float>(a, g, nw, bl, ldo, s);
+      else launch_bs<SCOUP_BF16, uint16_t>(a, g, nw, bl, ldo, s);
     } else {
-      if (a.out_dtype == SCOUP_F32) BS_LAUNCH(SCOUP_FP8_E4M3, float); else BS_LAUNCH(SCOUP_FP8_E4M3, uint16_t);
+      if (a.out_dtype == SCOUP_F32) launch_bs<SCOUP_FP8_E4M3, float>(a, g, nw, bl, ldo, s);
+      else launch_bs<SCOUP_FP8_E4M3, uint16_t>(a, g, nw, bl, ldo, s);
     }
-#undef BS_LAUNCH
     StageTimer::end(stage, s);
     return hipGetLastError();
   }
