@@ -196,12 +196,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
     const FT* Bf = reinterpret_cast<const FT*>(Bp);
 #pragma unroll
     for (int c = 0; c < NC; ++c) bcur[c] = Bf[((long long)(cb + c) * nks + k0 / F::KS) * 64 + lane];
+    const int ks_last = (k0 + kcur) / F::KS - 1;
     for (int kk = 0; kk < kcur; kk += F::KS) {
       const int ks = (k0 + kk) / F::KS;
-      if (kk + F::KS < kcur) {
+      // unconditional (the last step reloads its own fragment): a fixed count
+      // of loads per step lets each multiply wait for its own fragment only
+      const int ksn = min(ks + 1, ks_last);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) bnext[c] = Bf[((long long)(cb + c) * nks + ks + 1) * 64 + lane];
-      }
+      for (int c = 0; c < NC; ++c) bnext[c] = Bf[((long long)(cb + c) * nks + ksn) * 64 + lane];
       const int kb = (kk + (lane >> 5) * (F::KS / 2)) * F::ES;   // byte offset in the LDS row
       const FT a0 = *reinterpret_cast<const FT*>(sA + (rh * 64 + (lane & 31)) * row_bytes + kb);
       const FT a1 = *reinterpret_cast<const FT*>(sA + (rh * 64 + 32 + (lane & 31)) * row_bytes + kb);
