@@ -410,30 +410,44 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
   for (int t = threadIdx.x; t < n_tiles; t += kCountThreads) row[t] = (h[t >> 1] >> (16 * (t & 1))) & 0xFFFFu;
 }
 
-// hist[w][t] <- sum of hist[w'][t] over w' < w; tile_len[t] <- sum over all w
+// hist[w][t] <- sum of hist[w'][t] over w' < w; tile_len[t] <- sum over all w.
+// A workgroup covers 256 / nseg consecutive tiles; thread (seg, tile) holds
+// the 32 counts of workgroups 32 seg .. 32 seg + 31 of its tile in registers
+// (one round of loads), the segments' totals meet in LDS.
+constexpr int kColSeg = 32;                  // counting workgroups per segment
+__host__ __device__ inline int colscan_tiles_per_wg(int n_wg) { return 256 / ((n_wg + kColSeg - 1) / kColSeg); }
+
 __global__ __launch_bounds__(256) void k_bin_colscan(unsigned int* __restrict__ hist, int n_wg, int n_tiles,
                                                      unsigned int* __restrict__ tile_len, const Status* st) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_tiles) return;
-  if (st->view_overflow) { tile_len[t] = 0u; return; }     // empty lists; the view is retried
+  __shared__ unsigned int part[256];
+  const int nseg = (n_wg + kColSeg - 1) / kColSeg;   // <= 256 / 8
+  const int tpb = 256 / nseg;
+  const int tl = threadIdx.x % tpb, seg = threadIdx.x / tpb;
+  const int t = blockIdx.x * tpb + tl;
+  const bool act = seg < nseg && t < n_tiles;
+  if (st->view_overflow) {                     // empty lists; the view is retried
+    if (act && seg == 0) tile_len[t] = 0u;
+    return;
+  }
+  const int w0 = seg * kColSeg;
+  unsigned int v[kColSeg];
+  unsigned int sum = 0u;
+#pragma unroll
+  for (int k = 0; k < kColSeg; ++k) {
+    v[k] = act && w0 + k < n_wg ? hist[(long long)(w0 + k) * n_tiles + t] : 0u;
+    sum += v[k];
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (!act) return;
   unsigned int run = 0u;
-  int w = 0;
-  for (; w + 8 <= n_wg; w += 8) {
-    unsigned int v[8];
+  for (int q = 0; q < seg; ++q) run += part[q * tpb + tl];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = hist[(long long)(w + k) * n_tiles + t];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      hist[(long long)(w + k) * n_tiles + t] = run;
-      run += v[k];
-    }
+  for (int k = 0; k < kColSeg; ++k) {
+    if (w0 + k < n_wg) hist[(long long)(w0 + k) * n_tiles + t] = run;
+    run += v[k];
   }
-  for (; w < n_wg; ++w) {
-    const unsigned int v = hist[(long long)w * n_tiles + t];
-    hist[(long long)w * n_tiles + t] = run;
-    run += v;
-  }
-  tile_len[t] = run;
+  if (seg == nseg - 1) tile_len[t] = run;
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, long long n,
@@ -456,12 +470,24 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, lon
   const long long i0 = (long long)blockIdx.x * per_wg;
   const long long i1 = min(n, i0 + per_wg);
   long long i = i0 + threadIdx.x;
-  GSplat g_next;                                     // the thread's next splat, loaded an iteration ahead
-  if (i < i1) g_next = splats[i];
+  // the thread's next splat and pair offset, loaded an iteration ahead (the
+  // offset is written over the splat's depth before this iteration's key
+  // stores, so waiting for it never waits for them)
+  GSplat g_next;
+  unsigned int off_next = 0u;
+  if (i < i1) {
+    g_next = splats[i];
+    if (pair_off) off_next = pair_off[i];
+  }
   for (; i < i1; i += kCountThreads) {
     const GSplat g = g_next;
-    if (i + kCountThreads < i1) g_next = splats[i + kCountThreads];
+    const unsigned int off = off_next;
+    if (i + kCountThreads < i1) {
+      g_next = splats[i + kCountThreads];
+      if (pair_off) off_next = pair_off[i + kCountThreads];
+    }
     if (g.bx0 > g.bx1) continue;
+    if (pair_off) splats[i].depth_bits = off;        // the depth is in the keys now
     const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
     const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
     const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
@@ -475,7 +501,6 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, lon
         const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
         keys[(staged ? sb[t] : tile_start[t] + base[t]) + ticket] = key;
       }
-    if (pair_off) splats[i].depth_bits = pair_off[i];   // the depth is in the keys now
   }
 }
 
@@ -983,9 +1008,10 @@ __global__ __launch_bounds__(64 * W) void k_sort_lists_wg(unsigned long long* __
 // Counting path, one workgroup: exclusive scan of the block list lengths
 // (tile_start holds the lengths on entry, the starts on exit), the lists
 // longer than sort_cap (big_tiles), and the compositing order, longest list
-// first (as k_tile_order).  Thread i owns tiles [i c, i c + c): it reads
-// its lengths, and after the scan of the 1024 chunk sums rewrites them as
-// starts, keeping each tile's length bucket in LDS for the placement.
+// first (as k_tile_order).  Thread i owns tiles [i c, i c + c) and loads
+// their lengths into registers at once (C >= c, a compile-time bound, so the
+// loads issue together instead of one latency per tile); after the scan of
+// the 1024 chunk sums it rewrites them as starts and buckets them by length.
 // Exclusive scan of one value per thread over a 1024-thread workgroup:
 // shuffle scans inside the waves, then each thread adds the totals of the
 // waves before it (16 wave totals in LDS; two barriers).
@@ -1005,28 +1031,39 @@ __device__ __forceinline__ unsigned int block_exclusive_scan_1024(unsigned int x
   return before + inc - x;
 }
 
+template <int C>
 __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restrict__ tile_start, int n_tiles,
                                                           int sort_cap, unsigned int* __restrict__ big_tiles,
                                                           unsigned int* __restrict__ order, Status* st) {
   __shared__ unsigned int h[kOrderBuckets];
   __shared__ unsigned int wsum[16];
-  extern __shared__ unsigned short s_b[];      // [n_tiles] length buckets
   const int tid = threadIdx.x;
   for (int b = tid; b < kOrderBuckets; b += 1024) h[b] = 0u;
-  const int c = (n_tiles + 1023) / 1024;
+  const bool overflow = st->view_overflow != 0;
+  const int c = (n_tiles + 1023) / 1024;        // <= C
   const int t0 = min(n_tiles, tid * c), t1 = min(n_tiles, t0 + c);
+  unsigned int len[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {                // unconditional (clamped) loads, then the range test
+    const unsigned int x = tile_start[min(t0 + k, n_tiles - 1)];
+    len[k] = t0 + k < t1 ? x : 0u;
+  }
   unsigned int sum = 0u;
-  for (int t = t0; t < t1; ++t) sum += tile_start[t];
+#pragma unroll
+  for (int k = 0; k < C; ++k) sum += len[k];
   unsigned int run = block_exclusive_scan_1024(sum, wsum);   // (the bucket clears above are before its barriers)
   if (tid == 1023) tile_start[n_tiles] = run + sum;
-  for (int t = t0; t < t1; ++t) {
-    const unsigned int L = tile_start[t];
-    tile_start[t] = run;
-    run += L;
-    const int b = kOrderBuckets - 1 - (int)min(L, (unsigned int)(kOrderBuckets - 1));
-    s_b[t] = (unsigned short)b;
-    atomicAdd(&h[b], 1u);
-    if (L > (unsigned int)sort_cap && !st->view_overflow) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
+  auto bucket = [](unsigned int L) { return kOrderBuckets - 1 - (int)min(L, (unsigned int)(kOrderBuckets - 1)); };
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    const int t = t0 + k;
+    if (t < t1) {
+      const unsigned int L = len[k];
+      tile_start[t] = run;
+      run += L;
+      atomicAdd(&h[bucket(L)], 1u);
+      if (L > (unsigned int)sort_cap && !overflow) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
+    }
   }
   __syncthreads();
   if (!order) return;
@@ -1036,7 +1073,23 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
   h[2 * tid] = before;
   h[2 * tid + 1] = before + c0;
   __syncthreads();
-  for (int t = t0; t < t1; ++t) order[atomicAdd(&h[s_b[t]], 1u)] = (unsigned int)t;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    const int t = t0 + k;
+    if (t < t1) order[atomicAdd(&h[bucket(len[k])], 1u)] = (unsigned int)t;
+  }
+}
+
+// the per-thread tile bound of k_tile_scan_order
+static void launch_tile_scan_order(const BinArgs& a, hipStream_t s) {
+  const int c = (a.n_tiles + 1023) / 1024;
+#define TSO(C)                                                                                                  \
+  hipLaunchKernelGGL(k_tile_scan_order<C>, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.sort_cap,      \
+                     a.big_tiles, a.tile_order, a.status)
+  if (c <= 16) TSO(16);
+  else if (c <= 32) TSO(32);
+  else TSO(kCountMaxTiles / 1024);
+#undef TSO
 }
 
 hipError_t binning_set_lds_limits() {
@@ -1049,9 +1102,7 @@ hipError_t binning_set_lds_limits() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sizeof(unsigned short) * kOrderLdsTiles);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_tile_scan_order, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sizeof(unsigned short) * kCountMaxTiles);
+  return e;
 }
 
 static CullRecords cull_of(const BinArgs& a) {
@@ -1117,10 +1168,10 @@ hipError_t launch_bin_view(BinArgs& a, hipStream_t s) {
     const size_t lds = sizeof(unsigned int) * (size_t)((a.n_tiles + 1) / 2);
     hipLaunchKernelGGL(k_bin_count, dim3(nwg), dim3(kCountThreads), lds, s, a.splats, a.n, a.tiles_x, a.n_tiles,
                        a.tile_shift, a.cam.width, a.cam.height, per_wg, a.bin_hist, a.status);
-    hipLaunchKernelGGL(k_bin_colscan, dim3((a.n_tiles + 255) / 256), dim3(256), 0, s, a.bin_hist, nwg, a.n_tiles,
-                       a.tile_start, a.status);
-    hipLaunchKernelGGL(k_tile_scan_order, dim3(1), dim3(1024), sizeof(unsigned short) * (size_t)a.n_tiles, s,
-                       a.tile_start, a.n_tiles, a.sort_cap, a.big_tiles, a.tile_order, a.status);
+    const int cst = colscan_tiles_per_wg(nwg);
+    hipLaunchKernelGGL(k_bin_colscan, dim3((a.n_tiles + cst - 1) / cst), dim3(256), 0, s, a.bin_hist, nwg,
+                       a.n_tiles, a.tile_start, a.status);
+    launch_tile_scan_order(a, s);
     const size_t lds_place = lds + (a.n_tiles <= kCountPlaceLdsTiles ? sizeof(unsigned int) * (size_t)a.n_tiles : 0);
     hipLaunchKernelGGL(k_bin_place, dim3(nwg), dim3(kCountThreads), lds_place, s,
                        a.splats, a.n, a.tiles_x, a.n_tiles,
