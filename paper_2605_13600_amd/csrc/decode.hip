@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
                                                         int kpad, int kc, const uint8_t* __restrict__ Bp,
                                                         int n_valid, int ldo, TOut* __restrict__ out,
                                                         float out_mul, const float* __restrict__ cb_scale,
-                                                        int staged_out) {
+                                                        int staged_out, int ct_base) {
   using F = Mfma<T>;
   using FT = typename Frag<T>::type;
   extern __shared__ uint8_t sA[];                     // kDecBM rows of kc elements (+16 B pad)
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
   const int src_row = M * F::ES;
   const int rh = wave >> 2, cq = wave & 3;
   const int nks = kpad / F::KS;
-  const int ct0 = cq * NCT;
+  const int ct0 = ct_base + cq * NCT;             // the launch covers column tiles ct_base .. + 4 NCT - 1
   const long long n_tiles = (P + kDecBM - 1) / kDecBM;
   float mul = out_mul;
   if (cb_scale) mul /= *cb_scale;
@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
       // (free after the k loop), then all threads store whole rows, 16 bytes a lane
       constexpr int OES = (int)sizeof(TOut);
       constexpr int OSTRIDE = 128 * NCT * OES + 16;
-      const int cpr = n_valid * OES / 16;
+      const int col0 = ct_base * 32;               // the launch's first feature column
+      const int cpr = min(128 * NCT, n_valid - col0) * OES / 16;
 #pragma unroll
       for (int grp = 0; grp < 4; ++grp) {      // unrolled: acc[grp & 1] stays in registers
         if (rh == (grp >> 1)) {
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
           for (int c = 0; c < NCT; ++c)
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg) {
-              const int d0 = (ct0 + c) * 32 + 8 * rg + 4 * (lane >> 5);
+              const int d0 = (cq * NCT + c) * 32 + 8 * rg + 4 * (lane >> 5);   // column within the launch
               store4(row + d0, acc[a][c][4 * rg] * mul, acc[a][c][4 * rg + 1] * mul, acc[a][c][4 * rg + 2] * mul,
                      acc[a][c][4 * rg + 3] * mul);
             }
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(const uint8_t* __restric
           const int r = c / cpr, q = c - r * cpr;
           const long long p = p0 + grp * 32 + r;
           if (p < P)
-            *reinterpret_cast<i32x4*>(reinterpret_cast<uint8_t*>(out) + p * (long long)ldo * OES + q * 16) =
+            *reinterpret_cast<i32x4*>(reinterpret_cast<uint8_t*>(out) + (p * (long long)ldo + col0) * OES + q * 16) =
                 *reinterpret_cast<const i32x4*>(sA + r * OSTRIDE + q * 16);
         }
         __syncthreads();
@@ -559,13 +560,13 @@ static bool decode_staged_out(const DecodeArgs& a) {
 }
 
 template <int T, int NCT, typename TOut>
-static void launch_dec(const DecodeArgs& a, hipStream_t s, size_t lds, int grid) {
+static void launch_dec(const DecodeArgs& a, hipStream_t s, size_t lds, int grid, int ct_base = 0) {
   const bool staged = decode_staged_out<NCT, TOut>(a);
   if (staged) lds = std::max(lds, (size_t)32 * (128 * NCT * sizeof(TOut) + 16));
   hipLaunchKernelGGL((k_decode<T, NCT, TOut>), dim3(grid), dim3(kDecThreads), lds, s,
                      (const uint8_t*)a.coeff, a.P, a.m, a.kpad, decode_kchunk(a.m, a.in_dtype),
                      (const uint8_t*)a.codebook_prep, a.d, a.ldo > 0 ? a.ldo : a.d, (TOut*)a.out, a.out_mul,
-                     a.cb_scale, staged ? 1 : 0);
+                     a.cb_scale, staged ? 1 : 0, ct_base);
 }
 
 template <int T, typename TOut>
@@ -574,7 +575,10 @@ static hipError_t dispatch_nct(const DecodeArgs& a, hipStream_t s, size_t lds, i
     case 1: launch_dec<T, 1, TOut>(a, s, lds, grid); break;
     case 2: launch_dec<T, 2, TOut>(a, s, lds, grid); break;
     case 4: launch_dec<T, 4, TOut>(a, s, lds, grid); break;
-    case 8: launch_dec<T, 8, TOut>(a, s, lds, grid); break;
+    case 8:                                   // 1024 columns: two launches of 512 (eight column
+      launch_dec<T, 4, TOut>(a, s, lds, grid, 0);   // tiles a wave would spill their registers)
+      launch_dec<T, 4, TOut>(a, s, lds, grid, 16);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -617,8 +621,7 @@ hipError_t decode_set_lds_limits() {
 #define SETL(T, TO)                                                        \
   if ((e = set_lds<T, 1, TO>(b)) != hipSuccess) return e;                 \
   if ((e = set_lds<T, 2, TO>(b)) != hipSuccess) return e;                 \
-  if ((e = set_lds<T, 4, TO>(b)) != hipSuccess) return e;                 \
-  if ((e = set_lds<T, 8, TO>(b)) != hipSuccess) return e;
+  if ((e = set_lds<T, 4, TO>(b)) != hipSuccess) return e;
   SETL(SCOUP_F32, float) SETL(SCOUP_F32, uint16_t) SETL(SCOUP_BF16, float) SETL(SCOUP_BF16, uint16_t)
   SETL(SCOUP_FP8_E4M3, float) SETL(SCOUP_FP8_E4M3, uint16_t)
 #undef SETL
