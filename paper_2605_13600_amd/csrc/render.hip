@@ -167,11 +167,12 @@ __device__ __forceinline__ void store_rows(uint8_t* dst, const uint8_t* stage, i
   }
 }
 
-// three workgroups per CU (at most 168 registers) where the accumulators and
-// the decode's operands allow it, two otherwise
+// three workgroups per CU (at most 168 registers) for the map alone at up to
+// 256 atoms; two otherwise (a decode's W and staging leave LDS for two
+// workgroups anyway, so a tighter register bound would only spill)
 template <int ACC, int IN_T, int TPW>
 struct RWpe {
-  static constexpr int v = (TPW <= 2 && (IN_T == kNoDecode || IN_T == SCOUP_BF16)) ? 3 : 2;
+  static constexpr int v = (TPW <= 2 && IN_T == kNoDecode) ? 3 : 2;
 };
 
 template <int ACC, int IN_T, int TPW>
