@@ -832,15 +832,11 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int c = 0; c < NCH; ++c) fo[h][c] = (f16v){};
-    FT bcur[NCH];
+    auto load_b = [&](FT (&b)[NCH], int ks) {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) bcur[c] = Bf[((long long)(ct0 + c) * nks) * 64 + lane];
-    for (int ks = 0; ks < nks; ++ks) {
-      FT bnext[NCH];
-      if (ks + 1 < nks) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) bnext[c] = Bf[((long long)(ct0 + c) * nks + ks + 1) * 64 + lane];
-      }
+      for (int c = 0; c < NCH; ++c) b[c] = Bf[((long long)(ct0 + c) * nks + ks) * 64 + lane];
+    };
+    auto mma = [&](const FT (&b)[NCH], int ks) {
       FT af[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -849,12 +845,31 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
       }
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        fo[0][c] = FR::mfma(bcur[c], af[0], fo[0][c]);
-        fo[1][c] = FR::mfma(bcur[c], af[1], fo[1][c]);
+        fo[0][c] = FR::mfma(b[c], af[0], fo[0][c]);
+        fo[1][c] = FR::mfma(b[c], af[1], fo[1][c]);
       }
-      if (ks + 1 < nks) {
+    };
+    if ((nks & 1) == 0) {                        // alternating register sets (as in k_render)
+      FT b0[NCH], b1[NCH];
+      load_b(b0, 0);
+      for (int ks = 0; ks < nks; ks += 2) {
+        load_b(b1, ks + 1);
+        asm volatile("" ::: "memory");
+        mma(b0, ks);
+        load_b(b0, min(ks + 2, nks - 1));
+        asm volatile("" ::: "memory");
+        mma(b1, ks + 1);
+      }
+    } else {
+      FT bcur[NCH], bnext[NCH];
+      load_b(bcur, 0);
+      for (int ks = 0; ks < nks; ++ks) {
+        if (ks + 1 < nks) load_b(bnext, ks + 1);
+        mma(bcur, ks);
+        if (ks + 1 < nks) {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) bcur[c] = bnext[c];
+          for (int c = 0; c < NCH; ++c) bcur[c] = bnext[c];
+        }
       }
     }
     const int col0 = ps * PCOLS;                 // first feature column of the pass
