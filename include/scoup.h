@@ -201,7 +201,7 @@ size_t scoup_render_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam
  * coeff_dtype (F32, BF16 round-to-nearest-even, or FP8 E4M3 saturating; use
  * coeff_scale to place FP8 values in range, e.g. 256 since coefficients are
  * at most 1).
- *   topk_idx   device int32   [n*k], 1 <= k <= 16, indices < m_atoms (else SCOUP_E_DATA)
+ *   topk_idx   device int32   [n*k], 1 <= k <= 16, n*k < 2^30, indices < m_atoms (else SCOUP_E_DATA)
  *   topk_val   device float32 [n*k]
  *   coeff_map  device [H*W*m_atoms] of coeff_dtype, pixel-major (y*W + x)
  *   t_final    device float32 [H*W] transmittance left at each pixel, or NULL
@@ -234,7 +234,7 @@ size_t scoup_render_decode_workspace_bytes(int64_t n_gaussians, const scoup_came
  * rows from bfloat16-rounded products e * topk_val instead (one bfloat16
  * rounding per term; the result is still bit-reproducible).  Pixels without a
  * contribution get zero features.
- *   topk_idx/val   device [n*k], 1 <= k <= 16, indices < m_atoms (else SCOUP_E_DATA)
+ *   topk_idx/val   device [n*k], 1 <= k <= 16, n*k < 2^30, indices < m_atoms (else SCOUP_E_DATA)
  *   codebook       device float32 [m_atoms*dim], 1 <= m_atoms <= 512, 1 <= dim <= 1024
  *   coeff_map      device float32 [H*W*m_atoms] (the float32 W_hat, as for the
  *                  backward), or NULL

@@ -721,6 +721,7 @@ scoup_status render_impl(const scoup_gaussians* g, const int32_t* topk_idx, cons
   if (!cam) return fail(SCOUP_E_ARG, "camera is NULL");
   if ((st = check_camera(*cam, "camera")) != SCOUP_OK) return st;
   if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
+  if (g->n * (int64_t)k >= (int64_t(1) << 30)) return fail(SCOUP_E_ARG, "n * k must be below 2^30");
   if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
   if (g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");

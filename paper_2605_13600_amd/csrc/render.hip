@@ -231,8 +231,11 @@ k_render(const RenderBlockArgs a) {
       const int t = min(lane + 64 * r, nslots - 1);
       const int g = t / K, s = t - g * K;
       const unsigned int id = (unsigned int)__shfl((int)key, g, 64);
-      ci[r] = a.topk_idx[(long long)id * K + s];
-      cv[r] = a.topk_val[(long long)id * K + s];
+      // 32-bit byte offsets from the arrays' uniform bases (n k < 2^30, checked
+      // on the host): no per-lane 64-bit addresses to keep across the loop
+      const unsigned int off = (id * (unsigned int)K + (unsigned int)s) * 4u;
+      ci[r] = *reinterpret_cast<const int*>(reinterpret_cast<const uint8_t*>(a.topk_idx) + off);
+      cv[r] = *reinterpret_cast<const float*>(reinterpret_cast<const uint8_t*>(a.topk_val) + off);
     }
   };
   unsigned int key1 = 0u;
@@ -651,8 +654,11 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
       const int t = min(lane + 64 * r, nslots - 1);
       const int g = t / K, s = t - g * K;
       const unsigned int id = (unsigned int)__shfl((int)key, g, 64);
-      ci[r] = a.topk_idx[(long long)id * K + s];
-      cv[r] = a.topk_val[(long long)id * K + s];
+      // 32-bit byte offsets from the arrays' uniform bases (n k < 2^30, checked
+      // on the host): no per-lane 64-bit addresses to keep across the loop
+      const unsigned int off = (id * (unsigned int)K + (unsigned int)s) * 4u;
+      ci[r] = *reinterpret_cast<const int*>(reinterpret_cast<const uint8_t*>(a.topk_idx) + off);
+      cv[r] = *reinterpret_cast<const float*>(reinterpret_cast<const uint8_t*>(a.topk_val) + off);
     }
   };
   unsigned int key1 = 0u;
