@@ -531,7 +531,7 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 // each run adds its region's code with LDS atomic adds.  Rows are written
 // back coalesced, Top-K and entropy read from LDS.
 // ---------------------------------------------------------------------------
-template <int NS>
+template <int NS, int QN>
 __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
   extern __shared__ float rows[];            // G * (M+1)
   const int M = a.m_atoms, stride = M + 1;
@@ -598,25 +598,29 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     if (j >= M) atomicOr(&a.status->data_error, 2u);
     else if (j >= 0) atomicAdd(&row[j], w * c);
   };
-  // Codes of up to 8 slots in 16-byte rows: a chunk's code loads are issued
-  // (unconditionally, an inactive lane reading region 0) before the previous
-  // chunk's adds, which use codes loaded one chunk earlier.
-  const bool piped = a.k_code <= 8 && a.r_total > 0 && (a.k_code & 3) == 0 &&
+  // Codes of up to 4 QN slots in 16-byte rows (QN quads): a chunk's code
+  // loads are issued (unconditionally, an inactive lane reading region 0,
+  // quads past k_code re-reading the first) before the previous chunk's
+  // adds, which use codes loaded one chunk earlier.
+  const bool piped = a.k_code <= 4 * QN && a.r_total > 0 && (a.k_code & 3) == 0 &&
                      ((reinterpret_cast<uintptr_t>(a.code_idx) | reinterpret_cast<uintptr_t>(a.code_val)) & 15) == 0;
+  const int nq = a.k_code >> 2;                // code quads per region (piped)
   bool p_act = false;
   int p_g = 0;
   float p_w = 0.0f;
-  int4 p_j0 = make_int4(-1, -1, -1, -1), p_j1 = p_j0;
-  float4 p_c0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), p_c1 = p_c0;
+  int4 p_j[QN];
+  float4 p_c[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) { p_j[q] = make_int4(-1, -1, -1, -1); p_c[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f); }
   auto add_pending = [&]() {
     if (!p_act) return;
     float* row = rows + p_g * stride;
-    add_code(row, p_w, p_j0.x, p_c0.x); add_code(row, p_w, p_j0.y, p_c0.y);
-    add_code(row, p_w, p_j0.z, p_c0.z); add_code(row, p_w, p_j0.w, p_c0.w);
-    if (a.k_code > 4) {
-      add_code(row, p_w, p_j1.x, p_c1.x); add_code(row, p_w, p_j1.y, p_c1.y);
-      add_code(row, p_w, p_j1.z, p_c1.z); add_code(row, p_w, p_j1.w, p_c1.w);
-    }
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      if (q < nq) {
+        add_code(row, p_w, p_j[q].x, p_c[q].x); add_code(row, p_w, p_j[q].y, p_c[q].y);
+        add_code(row, p_w, p_j[q].z, p_c[q].z); add_code(row, p_w, p_j[q].w, p_c[q].w);
+      }
   };
   auto add_chunk = [&](unsigned int r, unsigned int r1, float2 rc) {
     int g, reg;
@@ -624,14 +628,18 @@ __global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
     const bool act = fold(r, r1, rc, g, reg, w);
     if (piped) {
       const long long gr = (long long)(act ? reg : 0) * a.k_code;
-      const int4 j0 = *reinterpret_cast<const int4*>(a.code_idx + gr);
-      const float4 c0 = *reinterpret_cast<const float4*>(a.code_val + gr);
-      const long long g1 = a.k_code > 4 ? gr + 4 : gr;
-      const int4 j1 = *reinterpret_cast<const int4*>(a.code_idx + g1);
-      const float4 c1 = *reinterpret_cast<const float4*>(a.code_val + g1);
+      int4 j[QN];
+      float4 c[QN];
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const long long gq = q < nq ? gr + 4 * q : gr;
+        j[q] = *reinterpret_cast<const int4*>(a.code_idx + gq);
+        c[q] = *reinterpret_cast<const float4*>(a.code_val + gq);
+      }
       add_pending();
       p_act = act; p_g = g; p_w = w;
-      p_j0 = j0; p_j1 = j1; p_c0 = c0; p_c1 = c1;
+#pragma unroll
+      for (int q = 0; q < QN; ++q) { p_j[q] = j[q]; p_c[q] = c[q]; }
       return;
     }
     if (!act) return;
@@ -956,6 +964,19 @@ int rowbuild_group(int m) {
   return g;
 }
 
+// the instance for the Top-K width (NS 64-entry slices of a row) and the
+// piped code quads (two up to 8 code slots, four up to 16)
+template <int QN>
+static void launch_rowbuild_ns(const RowBuildArgs& a, int G, int grid, size_t lds, int ns, hipStream_t s) {
+  if (ns <= 1) hipLaunchKernelGGL((k_rowbuild<1, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 2) hipLaunchKernelGGL((k_rowbuild<2, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 4) hipLaunchKernelGGL((k_rowbuild<4, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 8) hipLaunchKernelGGL((k_rowbuild<8, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 16) hipLaunchKernelGGL((k_rowbuild<16, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else if (ns <= 32) hipLaunchKernelGGL((k_rowbuild<32, QN>), dim3(grid), dim3(256), lds, s, a, G);
+  else hipLaunchKernelGGL((k_rowbuild<64, QN>), dim3(grid), dim3(256), lds, s, a, G);
+}
+
 hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int G = rowbuild_group(a.m_atoms);
@@ -963,13 +984,8 @@ hipError_t launch_rowbuild(const RowBuildArgs& a, hipStream_t s) {
   const size_t lds = sizeof(float) * (size_t)G * (a.m_atoms + 1);
   const int ns = (a.m_atoms + 63) / 64;
   StageTimer::begin(kStRowBuild, s);
-  if (ns <= 1) hipLaunchKernelGGL(k_rowbuild<1>, dim3(grid), dim3(256), lds, s, a, G);
-  else if (ns <= 2) hipLaunchKernelGGL(k_rowbuild<2>, dim3(grid), dim3(256), lds, s, a, G);
-  else if (ns <= 4) hipLaunchKernelGGL(k_rowbuild<4>, dim3(grid), dim3(256), lds, s, a, G);
-  else if (ns <= 8) hipLaunchKernelGGL(k_rowbuild<8>, dim3(grid), dim3(256), lds, s, a, G);
-  else if (ns <= 16) hipLaunchKernelGGL(k_rowbuild<16>, dim3(grid), dim3(256), lds, s, a, G);
-  else if (ns <= 32) hipLaunchKernelGGL(k_rowbuild<32>, dim3(grid), dim3(256), lds, s, a, G);
-  else hipLaunchKernelGGL(k_rowbuild<64>, dim3(grid), dim3(256), lds, s, a, G);
+  if (a.k_code > 8 && a.k_code <= 16) launch_rowbuild_ns<4>(a, G, grid, lds, ns, s);
+  else launch_rowbuild_ns<2>(a, G, grid, lds, ns, s);
   StageTimer::end(kStRowBuild, s);
   return hipGetLastError();
 }

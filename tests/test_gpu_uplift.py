@@ -189,10 +189,11 @@ def test_deferred_entry_overflow_adds_directly(limit):
         print(f"[entry limit {limit}, level {lvl}] acc={sa}")
 
 
-@pytest.mark.parametrize("m,kc", [(64, 5), (512, 16), (96, 3)])
-def test_code_widths_outside_the_pipelined_row_build(m, kc):
-    """Codes of K_code slots that are not a multiple of four or exceed eight
-    (the row build's scalar code loads), over codebooks of M atoms, full oracle."""
+@pytest.mark.parametrize("m,kc", [(64, 5), (512, 16), (96, 3), (64, 12)])
+def test_code_widths_of_the_row_build(m, kc):
+    """Codes of K_code slots over codebooks of M atoms, full oracle: widths
+    that are not a multiple of four (the row build's scalar code loads) and
+    12 or 16 (four code quads loaded a chunk ahead, 12 re-reading one)."""
     require_gpu()
     sc = sg.make_scene("tiny", res=(70, 45))
     v = sg.make_views(600 + kc, sc.views.cameras, 40, m, kc, hole_sites=1)
