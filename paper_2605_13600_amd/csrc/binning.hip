@@ -32,6 +32,7 @@ constexpr int kCountThreads = 1024;
 constexpr int kCountGroups = 256;          // workgroups of the counting pass (at least)
 constexpr int kCountMaxTiles = 49152;      // 16-bit LDS counters: 96 KB
 constexpr int kCountPlaceLdsTiles = 24576;  // placing pass: tile starts + bases in LDS up to here (96 KB more)
+constexpr int kScanLdsTiles = 32768;        // block-length scan: lengths staged in LDS up to here (128 KB)
 
 // the uplift's record arrays of the current view, per level (pairs whose
 // block the Gaussian cannot reach are never composited: zero records)
@@ -1037,16 +1038,31 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
                                                           unsigned int* __restrict__ order, Status* st) {
   __shared__ unsigned int h[kOrderBuckets];
   __shared__ unsigned int wsum[16];
+  extern __shared__ unsigned int s_len[];      // staged: the lengths, then the starts (n_tiles words)
   const int tid = threadIdx.x;
   for (int b = tid; b < kOrderBuckets; b += 1024) h[b] = 0u;
   const bool overflow = st->view_overflow != 0;
+  constexpr bool staged = 1024 * C <= kScanLdsTiles;   // every size this instance takes fits
   const int c = (n_tiles + 1023) / 1024;        // <= C
   const int t0 = min(n_tiles, tid * c), t1 = min(n_tiles, t0 + c);
   unsigned int len[C];
+  if constexpr (staged) {
+    // coalesced: thread i moves words i, i + 1024, ... (C loads in flight),
+    // then reads its own chunk from LDS
 #pragma unroll
-  for (int k = 0; k < C; ++k) {                // unconditional (clamped) loads, then the range test
-    const unsigned int x = tile_start[min(t0 + k, n_tiles - 1)];
-    len[k] = t0 + k < t1 ? x : 0u;
+    for (int k = 0; k < C; ++k) len[k] = tile_start[min(tid + 1024 * k, n_tiles - 1)];
+#pragma unroll
+    for (int k = 0; k < C; ++k)
+      if (tid + 1024 * k < n_tiles) s_len[tid + 1024 * k] = len[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < C; ++k) len[k] = t0 + k < t1 ? s_len[t0 + k] : 0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {              // unconditional (clamped) loads, then the range test
+      const unsigned int x = tile_start[min(t0 + k, n_tiles - 1)];
+      len[k] = t0 + k < t1 ? x : 0u;
+    }
   }
   unsigned int sum = 0u;
 #pragma unroll
@@ -1059,13 +1075,15 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
     const int t = t0 + k;
     if (t < t1) {
       const unsigned int L = len[k];
-      tile_start[t] = run;
+      if (staged) s_len[t] = run; else tile_start[t] = run;
       run += L;
       atomicAdd(&h[bucket(L)], 1u);
       if (L > (unsigned int)sort_cap && !overflow) big_tiles[atomicAdd(&st->n_big, 1u)] = (unsigned int)t;
     }
   }
   __syncthreads();
+  if (staged)                                   // the starts out, coalesced
+    for (int j = tid; j < n_tiles; j += 1024) tile_start[j] = s_len[j];
   if (!order) return;
   // exclusive scan of the buckets: two per thread, then across threads
   const unsigned int c0 = h[2 * tid], c1 = h[2 * tid + 1];
@@ -1083,8 +1101,9 @@ __global__ __launch_bounds__(1024) void k_tile_scan_order(unsigned int* __restri
 // the per-thread tile bound of k_tile_scan_order
 static void launch_tile_scan_order(const BinArgs& a, hipStream_t s) {
   const int c = (a.n_tiles + 1023) / 1024;
+  const size_t lds = c <= kScanLdsTiles / 1024 ? sizeof(unsigned int) * (size_t)a.n_tiles : 0;
 #define TSO(C)                                                                                                  \
-  hipLaunchKernelGGL(k_tile_scan_order<C>, dim3(1), dim3(1024), 0, s, a.tile_start, a.n_tiles, a.sort_cap,      \
+  hipLaunchKernelGGL(k_tile_scan_order<C>, dim3(1), dim3(1024), lds, s, a.tile_start, a.n_tiles, a.sort_cap,    \
                      a.big_tiles, a.tile_order, a.status)
   if (c <= 16) TSO(16);
   else if (c <= 32) TSO(32);
@@ -1102,7 +1121,16 @@ hipError_t binning_set_lds_limits() {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_tile_order, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)sizeof(unsigned short) * kOrderLdsTiles);
-  return e;
+  if (e != hipSuccess) return e;
+  const int scan_lds = (int)sizeof(unsigned int) * kScanLdsTiles;
+  if ((e = hipFuncSetAttribute((const void*)k_tile_scan_order<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               scan_lds)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_tile_scan_order<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               scan_lds)) != hipSuccess)
+    return e;
+  return hipFuncSetAttribute((const void*)k_tile_scan_order<kCountMaxTiles / 1024>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, scan_lds);
 }
 
 static CullRecords cull_of(const BinArgs& a) {
