@@ -377,6 +377,32 @@ __global__ __launch_bounds__(256) void k_clear_records(CullRecords cull, const S
 // tickets; the per-block sort by (depth, id) that follows makes the result
 // independent of it.
 // ---------------------------------------------------------------------------
+// Calls f(tx, ty) for every reachable block of Gaussian g's box: the first
+// 32 blocks (row-major) from its reachability bits, set bits only (the row
+// of a bit by a multiply-shift, exact for r < 32), then any further blocks
+// with the culling test itself (boxes of more than 32 blocks are rare).
+template <typename F>
+__device__ __forceinline__ void for_each_live_block(const GSplat& g, int tile_shift, int W, int H, F&& f) {
+  const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
+  const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
+  const int bw = tx1 - tx0 + 1, nb = bw * (ty1 - ty0 + 1);
+  const unsigned int inv = (65535u + (unsigned int)bw) / (unsigned int)bw;   // ceil(2^16 / bw)
+  unsigned int m = g.live & (nb >= 32 ? 0xFFFFFFFFu : ((1u << nb) - 1u));
+  while (m) {
+    const int r = __ffs(m) - 1;
+    m &= m - 1u;
+    const int ry = (int)(((unsigned int)r * inv) >> 16);
+    f(tx0 + r - ry * bw, ty0 + ry);
+  }
+  if (nb > 32) {
+    const BlockCull bc(g, tile_shift, W, H);
+    for (int r = 32; r < nb; ++r) {
+      const int ry = r / bw, tx = tx0 + r - ry * bw, ty = ty0 + ry;
+      if (bc.live(tx, ty)) f(tx, ty);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __restrict__ splats, long long n,
                                                              int tiles_x, int n_tiles, int tile_shift, int W, int H,
                                                              long long per_wg, unsigned int* __restrict__ hist,
@@ -395,16 +421,10 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(const GSplat* __res
     const GSplat g = g_next;
     if (i + kCountThreads < i1) g_next = splats[i + kCountThreads];
     if (g.bx0 > g.bx1) continue;
-    const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
-    const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
-    const BlockCull bc(g, tile_shift, W, H);
-    int r = 0;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx, ++r) {
-        if (!pair_live(g, bc, r, tx, ty)) continue;
-        const int t = ty * tiles_x + tx;
-        atomicAdd(&h[t >> 1], 1u << (16 * (t & 1)));
-      }
+    for_each_live_block(g, tile_shift, W, H, [&](int tx, int ty) {
+      const int t = ty * tiles_x + tx;
+      atomicAdd(&h[t >> 1], 1u << (16 * (t & 1)));
+    });
   }
   __syncthreads();
   unsigned int* row = hist + (long long)blockIdx.x * n_tiles;
@@ -490,18 +510,12 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_place(GSplat* splats, lon
     if (g.bx0 > g.bx1) continue;
     if (pair_off) splats[i].depth_bits = off;        // the depth is in the keys now
     const unsigned long long key = ((unsigned long long)g.depth_bits << 32) | (unsigned long long)i;
-    const int tx0 = g.bx0 >> tile_shift, tx1 = g.bx1 >> tile_shift;
-    const int ty0 = g.by0 >> tile_shift, ty1 = g.by1 >> tile_shift;
-    const BlockCull bc(g, tile_shift, W, H);
-    int r = 0;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx, ++r) {
-        if (!pair_live(g, bc, r, tx, ty)) continue;
-        const int t = ty * tiles_x + tx;
-        const unsigned int sh = 16 * (t & 1);
-        const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
-        keys[(staged ? sb[t] : tile_start[t] + base[t]) + ticket] = key;
-      }
+    for_each_live_block(g, tile_shift, W, H, [&](int tx, int ty) {
+      const int t = ty * tiles_x + tx;
+      const unsigned int sh = 16 * (t & 1);
+      const unsigned int ticket = (atomicAdd(&h[t >> 1], 1u << sh) >> sh) & 0xFFFFu;
+      keys[(staged ? sb[t] : tile_start[t] + base[t]) + ticket] = key;
+    });
   }
 }
 
