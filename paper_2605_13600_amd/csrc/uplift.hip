@@ -529,10 +529,13 @@ __device__ __forceinline__ float row_entropy(const float* row, int m, int lane) 
 // lane finds its record's Gaussian by comparing against the G range starts
 // (wave-uniform), runs of equal (Gaussian, region) records are folded, and
 // each run adds its region's code with LDS atomic adds.  Rows are written
-// back coalesced, Top-K and entropy read from LDS.
+// back coalesced, Top-K and entropy read from LDS.  A wave's time goes to
+// waiting on its chunk chain (loads, then cross-lane steps), so the register
+// budget is set for more waves per SIMD: 64 VGPRs (eight waves) with two code
+// quads, 96 (five) with four; the few spills fall outside the view loop.
 // ---------------------------------------------------------------------------
 template <int NS, int QN>
-__global__ __launch_bounds__(256) void k_rowbuild(RowBuildArgs a, int G) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QN <= 2 ? 8 : 5))) void k_rowbuild(RowBuildArgs a, int G) {
   extern __shared__ float rows[];            // G * (M+1)
   const int M = a.m_atoms, stride = M + 1;
   const long long i0 = (long long)blockIdx.x * G;
