@@ -204,6 +204,17 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
             Ff, _, _, _ = P.render(dg, dti, dtv, dC, cam, in_dtype=dt, out_dtype=out_dt, want_t_final=False)
         torch.cuda.synchronize()
         t_f = time.perf_counter() - t0
+        del Ff
+        # the same views through scoup_render_views, 8 cameras a call, views in flight
+        vb = 8
+        Fv, _ = P.render_views(dg, dti, dtv, dC, cams[:min(vb, n_views)], in_dtype=dt, out_dtype=out_dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(0, n_views, vb):
+            Fv, _ = P.render_views(dg, dti, dtv, dC, cams[i:i + vb], in_dtype=dt, out_dtype=out_dt)
+        torch.cuda.synchronize()
+        t_fv = time.perf_counter() - t0
+        del Fv
         lib.scoup_stage_timing(1)
         for cam in cams[:min(5, n_views)]:
             P.render(dg, dti, dtv, dC, cam, in_dtype=dt, out_dtype=out_dt, want_t_final=False)
@@ -223,6 +234,7 @@ def bench_render_decode(n_views, gaussians, lib, P, sg, torch, np):
         f_bytes = gaussians.n * (48 + 8 * k) + px * d * (4 if out_dt == "f32" else 2)
         res[dt].update({
             "fused_render_mpix_s": round(px * n_views / t_f / 1e6, 2),
+            "fused_render_views_mpix_s": round(px * n_views / t_fv / 1e6, 2),
             "fused_kernel_avg_us": round(fk_us, 1),
             "fused_kernel_hbm_frac": round(f_bytes / (fk_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             "fused_kernel_tflops": round(2.0 * px * m * d / (fk_us * 1e-6) / 1e12, 1),

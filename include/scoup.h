@@ -251,6 +251,34 @@ scoup_status scoup_render(const scoup_gaussians* g, const int32_t* topk_idx, con
                           scoup_dtype out_dtype, void* ws, size_t ws_bytes, unsigned long long* n_contrib,
                           void* stream);
 
+/* Workspace bytes for scoup_render_views over n_views cameras of cam's image
+ * size: the converted codebook once, then one scoup_render_workspace_bytes
+ * set of binning buffers per view in flight (min(4, n_views) sets).        */
+size_t scoup_render_views_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t n_views,
+                                          int32_t m_atoms, int32_t dim, scoup_dtype in_dtype,
+                                          int64_t pair_capacity);
+
+/* scoup_render (Sec. 4.3, Eq. 7 then Eq. 8) for n_views cameras of one image
+ * size, without a coefficient map or t_final: view v's features are exactly
+ * those scoup_render gives for cams[v] with coeff_map NULL, bit for bit.  Up
+ * to scoup_views_in_flight() views run at once (view v on the caller's stream
+ * or one of the library's streams, each with its own binning buffers), so
+ * the projection and binning of one view overlap the render kernel of
+ * another; the call returns after every view is done.
+ *   cams           host [n_views], every camera of cams[0]'s width and height
+ *                  (else SCOUP_E_ARG)
+ *   features       device [n_views*H*W*dim] of out_dtype, view-major
+ *   ws, ws_bytes   at least scoup_render_views_workspace_bytes(...); each set
+ *                  gets an equal share of what remains after the codebook
+ *   n_contrib      device uint64 [1] (+=) contributions of all views, or NULL
+ * Other arguments and limits as scoup_render.  Returns SCOUP_E_WORKSPACE when
+ * a view has more pairs than a set holds (scoup_required_pair_capacity()
+ * gives the largest count); the features are then incomplete.             */
+scoup_status scoup_render_views(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val, int32_t k,
+                                const scoup_camera* cams, int32_t n_views, const float* codebook, int32_t m_atoms,
+                                int32_t dim, scoup_dtype in_dtype, void* features, scoup_dtype out_dtype, void* ws,
+                                size_t ws_bytes, unsigned long long* n_contrib, void* stream);
+
 /* Workspace bytes for scoup_decode (the codebook converted to in_dtype and
  * arranged in MFMA operand order).                                          */
 size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in_dtype);
@@ -368,7 +396,8 @@ int32_t scoup_stage_stats(int32_t stage, double* total_ms, int64_t* launches);
 void scoup_uplift_touch_stats(uint64_t* touches, uint64_t* lost, uint64_t* direct, uint64_t* views);
 
 /* Views in flight in the uplift (scoup_uplift, scoup_uplift_accumulate,
- * scoup_uplift_levels): up to k views of a view batch are projected, binned
+ * scoup_uplift_levels) and in scoup_render_views (whose results do not
+ * depend on k at all): up to k views of a view batch are projected, binned
  * and composited at the same time, each with its own binning buffers, view i
  * on lane i mod k; lane 0 runs on the call's stream, the others on streams
  * the library creates once per device (default priority) and orders against

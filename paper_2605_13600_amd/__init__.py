@@ -9,7 +9,8 @@ library; the first call does, and raises if the library was not built.
 """
 from .api import (  # noqa: F401
     DeviceGaussians, DeviceViews, ScoupError, camera_struct, decode, entropy, gaussians_to_device,
-    RenderDecode, relevancy, render, render_backward, render_coeff, render_decode, set_deferred_entry_limit,
+    RenderDecode, relevancy, render, render_backward, render_coeff, render_decode, render_views,
+    set_deferred_entry_limit,
     set_views_in_flight, stage_timing, topk, uplift, uplift_touch_stats,
     uplift_accumulate, uplift_dense, uplift_levels, views_in_flight, views_to_device,
 )

@@ -62,6 +62,11 @@ SIGNATURES = {
     "scoup_render": (C.c_int, [C.POINTER(Gaussians), C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Camera),
                                C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
+    "scoup_render_views_workspace_bytes": (C.c_size_t, [C.c_int64, C.POINTER(Camera), C.c_int32, C.c_int32,
+                                                        C.c_int32, C.c_int, C.c_int64]),
+    "scoup_render_views": (C.c_int, [C.POINTER(Gaussians), C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(Camera),
+                                     C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_void_p, C.c_int,
+                                     C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "scoup_decode_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int]),
     "scoup_decode": (C.c_int, [C.c_void_p, C.c_int, C.c_float, C.c_int64, C.c_int32, C.c_void_p, C.c_int32,
                                C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),

@@ -400,6 +400,44 @@ def render(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, c
     raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
 
 
+def render_views(g: DeviceGaussians, topk_idx: torch.Tensor, topk_val: torch.Tensor, codebook: torch.Tensor, cams,
+                 in_dtype: str = "bf16", out_dtype: str = "bf16", stream=None, workspace: Optional[Workspace] = None,
+                 pair_capacity: int = 0):
+    """``render`` for several cameras of one image size, views in flight
+    (Sec. 4.3, Eq. 7 then Eq. 8 per view).  Returns (features (V, H, W, D),
+    n_contrib over all views); view v equals ``render`` on cams[v]."""
+    lib = L.load()
+    dev = g.means.device
+    cams = list(cams)
+    nv = len(cams)
+    m, d = codebook.shape
+    k = int(topk_idx.shape[1])
+    H, W = (int(cams[0].height), int(cams[0].width)) if nv else (0, 0)
+    feat = torch.empty((nv, H, W, d), dtype=_TORCH_DT[out_dtype], device=dev)
+    if nv == 0:
+        return feat, 0
+    carr = (L.Camera * nv)(*[camera_struct(c) for c in cams])
+    ws = workspace or _workspace(dev)
+    gs = g.struct()
+    key = ("render", g.n, W, H)
+    cap = max(int(pair_capacity), _capacity_cache.get(key, 0))
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(4):
+        nbytes = lib.scoup_render_views_workspace_bytes(g.n, C.byref(carr[0]), nv, m, d, _DT[in_dtype], cap)
+        buf = ws.get(nbytes)
+        cnt.zero_()
+        st = lib.scoup_render_views(C.byref(gs), _ptr(topk_idx), _ptr(topk_val), k, carr, nv, _ptr(codebook), m, d,
+                                    _DT[in_dtype], _ptr(feat), _DT[out_dtype], _ptr(buf), buf.numel(), _ptr(cnt),
+                                    _stream(stream))
+        if st == L.E_WORKSPACE:
+            cap = int(lib.scoup_required_pair_capacity() * 1.25) + 1024
+            _capacity_cache[key] = cap
+            continue
+        _check(st)
+        return feat, int(cnt.item())
+    raise ScoupError(L.E_WORKSPACE, "workspace retry limit reached")
+
+
 def decode(coeff: torch.Tensor, codebook: torch.Tensor, in_dtype: str = "bf16", coeff_scale: float = 1.0,
            out_dtype: str = "bf16", stream=None, workspace: Optional[Workspace] = None) -> torch.Tensor:
     """Eq. 8: features = coeff @ codebook on MFMA.  ``coeff`` is (..., M) in

@@ -815,6 +815,126 @@ scoup_status scoup_render(const scoup_gaussians* g, const int32_t* topk_idx, con
                      in_dtype, features, out_dtype, ws, ws_bytes, n_contrib, stream);
 }
 
+size_t scoup_render_views_workspace_bytes(int64_t n_gaussians, const scoup_camera* cam, int32_t n_views,
+                                          int32_t m_atoms, int32_t dim, scoup_dtype in_dtype,
+                                          int64_t pair_capacity) {
+  if (n_views < 1) return 0;
+  const size_t one = scoup_render_decode_workspace_bytes(n_gaussians, cam, m_atoms, dim, in_dtype, pair_capacity);
+  if (!one) return 0;
+  const size_t pre = 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));
+  return pre + (size_t)std::min(kLanes, (int)n_views) * align256(one - pre);
+}
+
+// Several cameras of one size rendered as scoup_render does each, up to
+// kLanes views in flight: view v runs on lane v mod lanes (the caller's
+// stream or a library stream, each with its own set of binning buffers), so
+// one view's projection and binning overlap another's render kernel.  The
+// lanes share the converted codebook; one status read at the end.
+scoup_status scoup_render_views(const scoup_gaussians* g, const int32_t* topk_idx, const float* topk_val, int32_t k,
+                                const scoup_camera* cams, int32_t n_views, const float* codebook, int32_t m_atoms,
+                                int32_t dim, scoup_dtype in_dtype, void* features, scoup_dtype out_dtype, void* ws,
+                                size_t ws_bytes, unsigned long long* n_contrib, void* stream) {
+  g_err.clear();
+  scoup_status st = check_gaussians(g);
+  if (st != SCOUP_OK) return st;
+  if (in_dtype != SCOUP_F32 && in_dtype != SCOUP_BF16 && in_dtype != SCOUP_FP8_E4M3)
+    return fail(SCOUP_E_ARG, "unknown decode dtype");
+  if (out_dtype != SCOUP_F32 && out_dtype != SCOUP_BF16) return fail(SCOUP_E_ARG, "output dtype must be F32 or BF16");
+  if (dim < 1 || dim > 1024) return fail(SCOUP_E_UNSUPPORTED, "dim must be in [1, 1024]");
+  if (n_views < 0) return fail(SCOUP_E_ARG, "n_views < 0");
+  if (n_views == 0) return SCOUP_OK;
+  if (!cams) return fail(SCOUP_E_ARG, "cameras is NULL");
+  if (!codebook || !features) return fail(SCOUP_E_ARG, "codebook or features is NULL");
+  for (int v = 0; v < n_views; ++v) {
+    if ((st = check_camera(cams[v], "camera")) != SCOUP_OK) return st;
+    if (cams[v].width != cams[0].width || cams[v].height != cams[0].height)
+      return fail(SCOUP_E_ARG, "every camera must have the first camera's image size");
+  }
+  if (k < 1 || k > 16) return fail(SCOUP_E_ARG, "k must be in [1, 16]");
+  if (g->n * (int64_t)k >= (int64_t(1) << 30)) return fail(SCOUP_E_ARG, "n * k must be below 2^30");
+  if (m_atoms < 1 || m_atoms > 512) return fail(SCOUP_E_ARG, "m_atoms must be in [1, 512]");
+  if (g->n > 0 && (!topk_idx || !topk_val)) return fail(SCOUP_E_ARG, "Top-K arrays are NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(SCOUP_E_ARG, "workspace NULL or misaligned");
+  const size_t pre = 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));
+  if (ws_bytes <= pre) return fail(SCOUP_E_WORKSPACE, "workspace smaller than the converted codebook");
+  HIP_TRY(ensure_lds_limits());
+  const int shift = 3;
+  const int mt = tiles_of(cams[0].width, cams[0].height, shift);
+  // the pair capacity depends on the view count only, not on the in-flight setting
+  const int n_sets = std::min(kLanes, (int)n_views);
+  const size_t set_bytes = ((ws_bytes - pre) / (size_t)n_sets) & ~(size_t)255;
+  const long long capacity = capacity_for(g->n, mt, set_bytes);
+  if (capacity < 1) {
+    g_required_pairs = std::max<int64_t>(8 * g->n, 1 << 16);
+    return fail(SCOUP_E_WORKSPACE, "workspace smaller than the fixed part");
+  }
+  const BinLayout L = bin_layout(g->n, mt, capacity, 1, 0, false);
+  const int lanes = std::min(g_views_in_flight, n_sets);
+  SideStreams* side = nullptr;
+  if (lanes > 1) HIP_TRY(side_streams(&side));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t strm[kLanes] = {s};
+  for (int j = 1; j < lanes; ++j) strm[j] = side->s[j - 1];
+  char* base = static_cast<char*>(ws);
+  float* scale = reinterpret_cast<float*>(base);
+  void* prep = base + 256;
+  HIP_TRY(launch_prep_codebook(codebook, m_atoms, dim, in_dtype, prep, scale, s, 0));
+  RenderBlockArgs a[kLanes] = {};
+  for (int j = 0; j < lanes; ++j) {
+    RenderBlockArgs& aj = a[j];
+    fill_bin(aj.bin, g, base + pre + (size_t)j * set_bytes, L, capacity, shift, kSortCap);
+    aj.bin.tiles_x = (cams[0].width + 7) / 8;
+    aj.bin.n_tiles = mt;
+    aj.topk_idx = topk_idx; aj.topk_val = topk_val; aj.k = k; aj.m_atoms = m_atoms;
+    aj.map = nullptr; aj.map_dtype = SCOUP_F32; aj.map_scale = 1.0f; aj.t_final = nullptr;
+    aj.in_dtype = in_dtype;
+    aj.codebook_prep = prep;
+    aj.cb_scale = in_dtype == SCOUP_FP8_E4M3 ? scale : nullptr;
+    aj.d = dim; aj.kpad = decode_kpad(m_atoms, in_dtype); aj.npad = decode_npad(dim);
+    aj.q_scale = in_dtype == SCOUP_FP8_E4M3 ? 256.0f : 1.0f;
+    aj.out_mul = 1.0f / aj.q_scale;
+    aj.out_dtype = out_dtype;
+    HIP_TRY(hipMemsetAsync(aj.bin.status, 0, sizeof(Status), s));
+  }
+  if (lanes > 1) {                            // the other lanes start after the codebook and the clears
+    HIP_TRY(hipEventRecord(side->start, s));
+    for (int j = 1; j < lanes; ++j) HIP_TRY(hipStreamWaitEvent(strm[j], side->start, 0));
+  }
+  const size_t view_bytes = (size_t)cams[0].width * (size_t)cams[0].height * (size_t)dim *
+                            (out_dtype == SCOUP_F32 ? 4u : 2u);
+  for (int v = 0; v < n_views; ++v) {
+    RenderBlockArgs& av = a[v % lanes];
+    av.bin.cam = to_dev(cams[v]);
+    av.features = static_cast<char*>(features) + (size_t)v * view_bytes;
+    HIP_TRY(launch_render_block(av, strm[v % lanes], kStRender));
+  }
+  for (int j = 1; j < lanes; ++j) {
+    HIP_TRY(hipEventRecord(side->done[j - 1], strm[j]));
+    HIP_TRY(hipStreamWaitEvent(s, side->done[j - 1], 0));
+  }
+  Status hs[kLanes] = {};
+  for (int j = 0; j < lanes; ++j) {
+    if (n_contrib) HIP_TRY(launch_add_contrib(n_contrib, a[j].bin.status, s));
+    HIP_TRY(hipMemcpyAsync(&hs[j], a[j].bin.status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  StageTimer::collect();
+  bool over = false;
+  unsigned int need = 0, data = 0;
+  for (int j = 0; j < lanes; ++j) {
+    over = over || hs[j].any_overflow;
+    need = std::max(need, hs[j].max_pairs);
+    data |= hs[j].data_error;
+  }
+  if (over) {
+    g_required_pairs = (int64_t)need;
+    return fail(SCOUP_E_WORKSPACE, "pair capacity " + std::to_string(capacity) + " exceeded; need " +
+                                       std::to_string(need));
+  }
+  if (data & 4u) return fail(SCOUP_E_DATA, "a Top-K atom index is >= m_atoms");
+  return SCOUP_OK;
+}
+
 size_t scoup_decode_workspace_bytes(int32_t m_atoms, int32_t dim, scoup_dtype in_dtype) {
   if (m_atoms < 1 || dim < 1) return 0;
   return 256 + align256(decode_codebook_bytes(m_atoms, dim, in_dtype));

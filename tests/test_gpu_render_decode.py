@@ -214,3 +214,67 @@ def test_fused_render_full_view_against_oracle():
     assert stats["f32"][0] <= 1e-5
     assert stats["bf16"][0] <= 2e-2
     assert stats["fp8"][0] <= 2e-2
+
+
+@pytest.mark.parametrize("res,m,k,d", [((203, 77), 256, 8, 512), ((70, 45), 100, 5, 200)])
+def test_render_views_equal_single_view_renders(res, m, k, d):
+    """scoup_render_views (views in flight, each lane with its own binning
+    buffers) against scoup_render on each camera: six views (more than the
+    four lanes, so lanes are reused), every decode and output precision, bit
+    for bit, with four, three and one views in flight; contributions summed
+    over the views."""
+    require_gpu()
+    n = 8_000
+    g = sg.make_gaussians(11, n, (5.0, 5.0, 2.0), -3.6, 0.5, False, "beta")
+    cams = sg.orbit_cameras(12, 6, 12.0, 1.0, 4.0, 1.0, 0.5, res[0], res[1], 60.0)
+    ti, tv = sg.random_topk(13, n, m, k)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    Ct = torch.from_numpy(sg.random_codebook(14, m, d)).cuda()
+    old = P.views_in_flight()
+    try:
+        for dt in ("f32", "bf16", "fp8"):
+            for out in ("f32", "bf16"):
+                iv = (lambda t: t.view(torch.int16)) if out == "bf16" else (lambda t: t.view(torch.int32))
+                refs, nc_sum = [], 0
+                for cam in cams:
+                    F, _, _, nc = P.render(dg, dti, dtv, Ct, cam, in_dtype=dt, out_dtype=out, want_t_final=False)
+                    refs.append(F)
+                    nc_sum += nc
+                for lanes in (4, 3, 1):
+                    P.set_views_in_flight(lanes)
+                    Fv, ncv = P.render_views(dg, dti, dtv, Ct, cams, in_dtype=dt, out_dtype=out)
+                    torch.cuda.synchronize()
+                    assert Fv.shape == (len(cams), res[1], res[0], d)
+                    for v, F in enumerate(refs):
+                        assert torch.equal(iv(Fv[v]), iv(F)), (dt, out, lanes, v)
+                    assert ncv == nc_sum, (dt, out, lanes)
+    finally:
+        P.set_views_in_flight(old)
+    print(f"[render views {res} M={m} K={k} D={d}] 6 views equal single-view renders")
+
+
+def test_render_views_edge_cases():
+    """No views: an empty result.  Cameras of different image sizes: an
+    argument error.  A pair capacity below what a view needs: the workspace
+    error, and the binding's retry gives the single-view results."""
+    require_gpu()
+    n, m, k, d = 6_000, 64, 4, 128
+    g = sg.make_gaussians(21, n, (5.0, 5.0, 2.0), -3.6, 0.5, False, "beta")
+    cams = sg.orbit_cameras(22, 3, 12.0, 1.0, 4.0, 1.0, 0.5, 96, 64, 60.0)
+    other = sg.orbit_cameras(23, 1, 12.0, 1.0, 4.0, 1.0, 0.5, 80, 64, 60.0)
+    ti, tv = sg.random_topk(24, n, m, k)
+    dg = P.gaussians_to_device(g)
+    dti, dtv = torch.from_numpy(ti).cuda(), torch.from_numpy(tv).cuda()
+    Ct = torch.from_numpy(sg.random_codebook(25, m, d)).cuda()
+    F0, nc0 = P.render_views(dg, dti, dtv, Ct, [])
+    assert F0.shape[0] == 0 and nc0 == 0
+    with pytest.raises(P.ScoupError):
+        P.render_views(dg, dti, dtv, Ct, list(cams) + list(other))
+    from paper_2605_13600_amd import api as A
+    A._capacity_cache.pop(("render", n, 96, 64), None)
+    Fv, ncv = P.render_views(dg, dti, dtv, Ct, cams, workspace=A.Workspace(dg.means.device), pair_capacity=64)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        F, _, _, _ = P.render(dg, dti, dtv, Ct, cam, want_t_final=False)
+        assert torch.equal(Fv[v].view(torch.int16), F.view(torch.int16)), v
