@@ -597,9 +597,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QN <= 2 ? 8
     }
     return valid && (lane >= 62 || next_head);
   };
+  // branch-free: a slot outside [0, M) adds zero to the row's pad entry M
+  // (never written back); an index >= M is flagged once per wave at the end
+  bool code_err = false;
   auto add_code = [&](float* row, float w, int j, float c) {
-    if (j >= M) atomicOr(&a.status->data_error, 2u);
-    else if (j >= 0) atomicAdd(&row[j], w * c);
+    code_err |= j >= M;
+    const bool ok = (unsigned int)j < (unsigned int)M;
+    atomicAdd(&row[ok ? j : M], ok ? w * c : 0.0f);
   };
   // Codes of up to 4 QN slots in 16-byte rows (QN quads): a chunk's code
   // loads are issued (unconditionally, an inactive lane reading region 0,
@@ -694,6 +698,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QN <= 2 ? 8
     rc_c = rc_n; rc_c2 = rc_n2;
   }
   add_pending();
+  if (__ballot(code_err) != 0ull && lane == 0) atomicOr(&a.status->data_error, 2u);
   __syncthreads();
   for (int j = tid; j < gn * M; j += 256) acc[j] = rows[(j / M) * stride + (j % M)];
   if (a.k_top > 0) {

@@ -275,6 +275,20 @@ def test_bad_region_id_is_reported():
     assert ei.value.status == -5
 
 
+def test_bad_code_atom_index_is_reported():
+    """A code slot whose atom index is >= m_atoms (every region's first slot):
+    the row build leaves it out and the call reports the data error."""
+    require_gpu()
+    sc = sg.make_scene("tiny")
+    ci = sc.views.code_idx.copy()
+    ci[:, 0] = 64
+    v = sg.Views(sc.views.cameras, sc.views.region_maps, sc.views.region_base, ci, sc.views.code_val, 64)
+    dg, dv = to_device(sc.gaussians, v)
+    with pytest.raises(P.ScoupError) as ei:
+        P.uplift_accumulate(dg, dv)
+    assert ei.value.status == -5 and "code atom" in str(ei.value)
+
+
 @pytest.mark.parametrize("m,k", [(64, 4), (100, 7), (256, 8), (512, 16), (1000, 64)])
 def test_topk_kernel_against_oracle_exact(m, k):
     """Top-K alone on a seeded float32 matrix with exact ties and zero rows: indices
