@@ -134,8 +134,7 @@ __device__ __forceinline__ void put4(uint8_t* p, int t, float a, float b, float 
     const unsigned int hi = (unsigned int)f32_to_bf16_rne(c) | ((unsigned int)f32_to_bf16_rne(d) << 16);
     *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
   } else {
-    *reinterpret_cast<unsigned int*>(p) = (unsigned int)f32_to_e4m3(a) | ((unsigned int)f32_to_e4m3(b) << 8) |
-                                          ((unsigned int)f32_to_e4m3(c) << 16) | ((unsigned int)f32_to_e4m3(d) << 24);
+    *reinterpret_cast<unsigned int*>(p) = f32x4_to_e4m3(a, b, c, d);
   }
 }
 
@@ -601,9 +600,9 @@ size_t render_mx_lds_bytes(int m, int kpad, int npad, int in_t, int out_t) {
   return std::max(mx_region_a(tpw <= 1 ? 1 : tpw <= 2 ? 2 : 4), mx_region_b(kpad, m, npad, in_t, out_t)) + kRCtrl;
 }
 
-// three workgroups per CU (at most 168 registers) for BF16 up to 256 atoms;
-// two otherwise (FP8's conversion of the rows needs more registers)
-template <int IN_T, int NCT, int TPW, int WPE = (TPW <= 2 && IN_T == SCOUP_BF16 ? 3 : 2)>
+// three workgroups per CU (at most 168 registers) for BF16 and FP8 up to 256
+// atoms; two otherwise
+template <int IN_T, int NCT, int TPW, int WPE = (TPW <= 2 ? 3 : 2)>
 __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))) void k_render_mx(
     const RenderBlockArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -799,10 +798,8 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
           const unsigned int hi = (unsigned int)f32_to_bf16_rne(v[4 * q + 2]) | ((unsigned int)f32_to_bf16_rne(v[4 * q + 3]) << 16);
           *reinterpret_cast<uint2*>(Wq + p * wrow + 2 * j0) = make_uint2(lo, hi);
         } else {
-          const unsigned int w4 = (unsigned int)f32_to_e4m3(v[4 * q] * a.q_scale) |
-                                  ((unsigned int)f32_to_e4m3(v[4 * q + 1] * a.q_scale) << 8) |
-                                  ((unsigned int)f32_to_e4m3(v[4 * q + 2] * a.q_scale) << 16) |
-                                  ((unsigned int)f32_to_e4m3(v[4 * q + 3] * a.q_scale) << 24);
+          const unsigned int w4 = f32x4_to_e4m3(v[4 * q] * a.q_scale, v[4 * q + 1] * a.q_scale,
+                                                v[4 * q + 2] * a.q_scale, v[4 * q + 3] * a.q_scale);
           *reinterpret_cast<unsigned int*>(Wq + p * wrow + j0) = w4;
         }
       }

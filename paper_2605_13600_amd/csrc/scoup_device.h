@@ -186,25 +186,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((unsigned int)b << 16); }
 
 // float32 -> OCP FP8 E4M3 (bias 7, 3 mantissa bits, max 448, no infinities),
-// round to nearest even, saturating to +-448.
+// round to nearest even, saturating to +-448: the hardware conversion
+// (v_cvt_pk_fp8_f32, round to nearest even, subnormals kept) of the value
+// clamped to +-448 first, since larger magnitudes would convert to NaN.
+__device__ __forceinline__ float e4m3_clamp(float x) { return x != x ? x : fminf(fmaxf(x, -448.0f), 448.0f); }
+
 __device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
-  const unsigned int u = __float_as_uint(x);
-  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
-  const float a = fabsf(x);
-  if (a != a) return (uint8_t)(sign | 0x7f);
-  if (a >= 464.0f) return (uint8_t)(sign | 0x7e);
-  if (a < 0.015625f) {                       // subnormal range: multiples of 2^-9
-    const int q = (int)rintf(a * 512.0f);    // 0..8, 8 becomes the smallest normal
-    return (uint8_t)(sign | q);
-  }
-  int e;
-  const float f = frexpf(a, &e);             // a = f 2^e, f in [0.5, 1)
-  int ex = e - 1;
-  int mq = (int)rintf((f * 2.0f - 1.0f) * 8.0f);
-  if (mq == 8) { mq = 0; ++ex; }
-  const int biased = ex + 7;
-  if (biased > 15 || (biased == 15 && mq == 7)) return (uint8_t)(sign | 0x7e);
-  return (uint8_t)(sign | (biased << 3) | mq);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(x), 0.0f, 0, false) & 0xff);
+}
+
+// four values, the first in the low byte
+__device__ __forceinline__ unsigned int f32x4_to_e4m3(float a, float b, float c, float d) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
+  return (unsigned int)__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), lo, true);
 }
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) {

@@ -76,6 +76,10 @@ def test_render_low_precision_outputs():
     assert (np.abs(b - a) <= 2.0 ** -8 * np.abs(a) + 1e-30).all()
     c = f8.view(torch.float8_e4m3fn).float().cpu().numpy().astype(np.float64) / sc
     assert (np.abs(c - a) <= 2.0 ** -3 * np.abs(a) + 2.0 ** -9 / sc).all()
+    # the map's FP8 bytes are the OCP E4M3 rounding (nearest even) of the float32
+    # rows times the power-of-two scale, bit for bit: torch's CPU conversion
+    ref8 = (f32.cpu() * sc).to(torch.float8_e4m3fn).view(torch.uint8)
+    assert sc == 256.0 and torch.equal(f8.cpu().view(torch.uint8), ref8)
 
 
 def _cos_err(F, R, mask=None):
