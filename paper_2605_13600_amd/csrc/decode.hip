@@ -122,8 +122,8 @@ __device__ __forceinline__ void store4(float* p, float a, float b, float c, floa
   *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
 }
 __device__ __forceinline__ void store4(uint16_t* p, float a, float b, float c, float d) {
-  const unsigned int lo = (unsigned int)f32_to_bf16_rne(a) | ((unsigned int)f32_to_bf16_rne(b) << 16);
-  const unsigned int hi = (unsigned int)f32_to_bf16_rne(c) | ((unsigned int)f32_to_bf16_rne(d) << 16);
+  const unsigned int lo = f32x2_to_bf16(a, b);
+  const unsigned int hi = f32x2_to_bf16(c, d);
   *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
 }
 

@@ -130,8 +130,8 @@ __device__ __forceinline__ void put4(uint8_t* p, int t, float a, float b, float 
   if (t == SCOUP_F32) {
     *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
   } else if (t == SCOUP_BF16) {
-    const unsigned int lo = (unsigned int)f32_to_bf16_rne(a) | ((unsigned int)f32_to_bf16_rne(b) << 16);
-    const unsigned int hi = (unsigned int)f32_to_bf16_rne(c) | ((unsigned int)f32_to_bf16_rne(d) << 16);
+    const unsigned int lo = f32x2_to_bf16(a, b);
+    const unsigned int hi = f32x2_to_bf16(c, d);
     *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
   } else {
     *reinterpret_cast<unsigned int*>(p) = f32x4_to_e4m3(a, b, c, d);
@@ -557,8 +557,8 @@ __device__ __forceinline__ void lds_store4(float* p, float a, float b, float c, 
   *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
 }
 __device__ __forceinline__ void lds_store4(uint16_t* p, float a, float b, float c, float d) {
-  const unsigned int lo = (unsigned int)f32_to_bf16_rne(a) | ((unsigned int)f32_to_bf16_rne(b) << 16);
-  const unsigned int hi = (unsigned int)f32_to_bf16_rne(c) | ((unsigned int)f32_to_bf16_rne(d) << 16);
+  const unsigned int lo = f32x2_to_bf16(a, b);
+  const unsigned int hi = f32x2_to_bf16(c, d);
   *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
 }
 
@@ -794,8 +794,8 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(WPE))
         const int j0 = tl * 32 + 8 * q + 4 * (lane >> 5);
         const f16v& v = acc[t][h];
         if constexpr (IN_T == SCOUP_BF16) {
-          const unsigned int lo = (unsigned int)f32_to_bf16_rne(v[4 * q]) | ((unsigned int)f32_to_bf16_rne(v[4 * q + 1]) << 16);
-          const unsigned int hi = (unsigned int)f32_to_bf16_rne(v[4 * q + 2]) | ((unsigned int)f32_to_bf16_rne(v[4 * q + 3]) << 16);
+          const unsigned int lo = f32x2_to_bf16(v[4 * q], v[4 * q + 1]);
+          const unsigned int hi = f32x2_to_bf16(v[4 * q + 2], v[4 * q + 3]);
           *reinterpret_cast<uint2*>(Wq + p * wrow + 2 * j0) = make_uint2(lo, hi);
         } else {
           const unsigned int w4 = f32x4_to_e4m3(v[4 * q] * a.q_scale, v[4 * q + 1] * a.q_scale,

@@ -175,12 +175,18 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return best;
 }
 
-// float32 -> bfloat16, round to nearest even (NaN kept quiet).
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// float32 -> bfloat16, round to nearest even (a NaN stays a NaN): the
+// hardware conversion (v_cvt_pk_bf16_f32), which on gfx950 rounds every
+// non-NaN float32, subnormals and overflow to infinity included, exactly as
+// adding 0x7fff plus the kept lowest bit and truncating does.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+
+// two values, the first in the low half
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned int f32x2_to_bf16(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(unsigned int, __builtin_convertvector(v, bf16x2_t));
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((unsigned int)b << 16); }
