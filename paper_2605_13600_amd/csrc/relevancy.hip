@@ -113,22 +113,18 @@ __global__ __launch_bounds__(256) void k_rel_prep(const float* __restrict__ C, i
   }
 }
 
-// exact OCP E4M3 -> bfloat16 bits (every E4M3 value is a bfloat16 value)
-__device__ __forceinline__ unsigned int e4m3_to_bf16_bits(unsigned int b) {
-  const unsigned int em = b & 0x7Fu;
-  const unsigned int sign = (b & 0x80u) << 8;
-  const unsigned int normal = (em << 4) + (120u << 7);               // exponent e - 7 + 127
-  const unsigned int sub = __float_as_uint((float)em * 0x1p-9f) >> 16;  // m 2^-9
-  return sign | (em >= 8u ? normal : sub);
-}
-
+// exact OCP E4M3 -> bfloat16 (every E4M3 value is a bfloat16 value): the
+// hardware decodes a byte pair to float32 (v_cvt_pk_f32_fp8), the exact
+// narrowing to bfloat16 packs the pair again
 __device__ __forceinline__ bf16x8 e4m3x8_to_bf16(i32x2 v) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
   i32x4 o;
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
-    const unsigned int x = (unsigned int)v[w];
-    o[2 * w] = (int)(e4m3_to_bf16_bits(x & 0xFFu) | (e4m3_to_bf16_bits((x >> 8) & 0xFFu) << 16));
-    o[2 * w + 1] = (int)(e4m3_to_bf16_bits((x >> 16) & 0xFFu) | (e4m3_to_bf16_bits(x >> 24) << 16));
+    const f2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(v[w], false);
+    const f2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(v[w], true);
+    o[2 * w] = (int)f32x2_to_bf16(lo[0], lo[1]);
+    o[2 * w + 1] = (int)f32x2_to_bf16(hi[0], hi[1]);
   }
   return __builtin_bit_cast(bf16x8, o);
 }
