@@ -542,7 +542,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QN <= 2 ? 8
   const int gn = (int)min((long long)G, a.n - i0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   float* acc = a.acc + i0 * M;
-  for (int j = tid; j < gn * M; j += 256) rows[(j / M) * stride + (j % M)] = acc[j];
+  for (int g = wave; g < gn; g += 4)          // one row a wave, lanes along the row
+    for (int j = lane; j < M; j += 64) rows[g * stride + j] = acc[(long long)g * M + j];
   __syncthreads();
   const unsigned int cap = (unsigned int)a.capacity;
   const bool vec = (a.k_code & 3) == 0 &&
@@ -700,7 +701,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QN <= 2 ? 8
   add_pending();
   if (__ballot(code_err) != 0ull && lane == 0) atomicOr(&a.status->data_error, 2u);
   __syncthreads();
-  for (int j = tid; j < gn * M; j += 256) acc[j] = rows[(j / M) * stride + (j % M)];
+  for (int g = wave; g < gn; g += 4)
+    for (int j = lane; j < M; j += 64) acc[(long long)g * M + j] = rows[g * stride + j];
   if (a.k_top > 0) {
     for (int g = wave; g < gn; g += 4)
       topk_row<NS>(rows + g * stride, M, a.k_top, lane, a.topk_idx + (i0 + g) * a.k_top,
